@@ -1,0 +1,198 @@
+/*
+ * countpairs.h - C ABI of the MI355X (gfx950) gridded pair-counting library.
+ *
+ * Operation (Sinha & Garrison, "Corrfunc: blazing fast correlation functions
+ * with AVX512F SIMD intrinsics"):
+ *   - Section 1.1, Code 1: the pair count is the histogram, over separation
+ *     bins, of all pairs (i, j) with R_min <= sep < R_max; each pair adds one
+ *     to its bin's count and its weight to the bin's weight sum.
+ *   - Section 1.1, eqn:separations: xi(r) bins r = |p_j - p_i|; wp(rp) bins
+ *     rp = sqrt(dx^2 + dy^2) and keeps pi = |dz| < pi_max (line of sight z).
+ *   - Section 1.2 and Section 2.1: points are gridded into cells; only
+ *     neighbouring cell pairs are searched; for an auto-count only unique
+ *     pairs are searched and the total is doubled.
+ *   - Section 2.2: cell pairs whose minimum possible separation (from the
+ *     cells' bounding boxes) is at least R_max are skipped.
+ *
+ * Conventions shared by every entry point (all readings of the paper):
+ *   - separations are compared squared: bin k holds E_k <= s < E_{k+1} with
+ *     E_k = fl64(e_k * e_k) and s = ((dx*dx + dy*dy) + dz*dz) evaluated in
+ *     binary64 without fused multiply-add; d = p_j - p_i per axis, wrapped to
+ *     the minimum image when periodic (d > L/2 -> d - L, d < -L/2 -> d + L).
+ *   - wp output is the 2-D histogram [rp bin][pi bin], rp-major, with pi bins
+ *     q_l <= pi < q_{l+1}, q_l = fl64(l * fl64(pi_max / npibins)) for
+ *     0 < l < npibins, q_0 = 0 and q_npibins = pi_max.
+ *   - counts are exact.  CP_PREC_FP32_RECHECK evaluates distances in binary32
+ *     with a derived error bound and re-evaluates in binary64 every pair whose
+ *     binary32 value could lie on the other side of an edge, so its counts are
+ *     identical to CP_PREC_FP64's.
+ *   - weighted outputs: wsum_k = sum of w_i * w_j, ravg_k = sum of
+ *     w_i * w_j * sep / wsum_k (sep = r for xi, rp for wp; 0 for empty bins).
+ *     They are binary64 sums in an unspecified order (relative error far
+ *     below 1e-12 for the supported sizes).  Absent weights mean w = 1.
+ *
+ * Memory: position and weight arrays are DEVICE pointers, owned by the
+ * caller, read-only for the call and not retained after it returns.  Edges
+ * and all outputs are HOST pointers.  Every countpairs_* call enqueues its
+ * work on options->stream (NULL: the null stream) and synchronises that
+ * stream before returning, so the status covers errors found on the device.
+ * Calls on different host threads with different streams are independent;
+ * each thread keeps its own cached device scratch buffers unless the caller
+ * supplies a workspace.
+ *
+ * Errors: every entry point returns CP_OK (0) or a negative CP_ERR_* code;
+ * countpairs_last_error() returns a thread-local message for the last failure.
+ * No call frees caller memory; no C++ exception crosses this boundary.
+ */
+#ifndef COUNTPAIRS_H
+#define COUNTPAIRS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* element type of cp_points.x/y/z */
+enum { CP_F64 = 0, CP_F32 = 1 };
+/* arithmetic of the distance evaluation */
+enum { CP_PREC_FP64 = 0, CP_PREC_FP32_RECHECK = 1 };
+/* auto-count convention: ordered pairs (each unordered pair counted twice,
+ * Section 2.1 "double the total number of pairs found at the end") or unique
+ * pairs (each unordered pair once) */
+enum { CP_ORDERED = 0, CP_UNIQUE = 1 };
+
+enum {
+  CP_OK = 0,
+  CP_ERR_INVALID_ARG = -1, /* bad edges, sizes, enums, box, null pointers */
+  CP_ERR_OUT_OF_BOX = -2,  /* periodic coordinate outside [0, boxsize) */
+  CP_ERR_NONFINITE = -3,   /* NaN or Inf in positions or weights */
+  CP_ERR_NOMEM = -4,       /* allocation failed or workspace too small */
+  CP_ERR_DEVICE = -5,      /* HIP runtime error (see countpairs_last_error) */
+  CP_ERR_INTERNAL = -6     /* a device-side consistency check failed */
+};
+
+/* A point set: n points, SoA coordinates (CP_F64: double, CP_F32: float),
+ * optional binary64 weights (NULL: unweighted).  Device pointers. */
+typedef struct {
+  int64_t n;
+  const void *x, *y, *z;
+  const double *w;
+  int dtype;
+} cp_points;
+
+typedef struct {
+  int precision;          /* CP_PREC_FP64 or CP_PREC_FP32_RECHECK */
+  int periodic;           /* 1: cube [0, boxsize)^3, minimum-image separations */
+  double boxsize;         /* side of the periodic cube (ignored otherwise) */
+  int refine[3];          /* cells per R_max (pi_max along z for wp) per axis;
+                             0 = library default (Section 3.1 bin_refine_factors) */
+  int need_ravg;          /* 1: fill wsum and ravg */
+  int count_mode;         /* CP_ORDERED (default) or CP_UNIQUE, auto-counts only */
+  void *stream;           /* hipStream_t; NULL = null stream */
+  void *workspace;        /* optional device scratch owned by the caller */
+  size_t workspace_bytes; /* its size; too small -> CP_ERR_NOMEM */
+} cp_options;
+
+/* Diagnostics of the last successful call on the calling thread. */
+typedef struct {
+  uint64_t candidates;       /* pair separations evaluated on the device */
+  uint64_t rechecks;         /* binary32 pairs re-evaluated in binary64 */
+  uint64_t cell_pairs;       /* (tile, cell) work units searched */
+  uint64_t cell_pairs_pruned;/* units skipped by the bounding-box test */
+  uint64_t tiles;            /* primary tiles of <= 64 points */
+  int grid[3];               /* cells per axis */
+  int refine[3];             /* refine factors used */
+  float ms_grid;             /* device time of the cell build (ms) */
+  float ms_pairs;            /* device time of the pair kernel (ms) */
+  float ms_total;            /* device time of the whole call (ms) */
+} cp_stats;
+
+/* Fill *o with defaults: FP32 recheck, non-periodic, refine 0 (library
+ * default), no ravg, ordered counts, null stream, library scratch. */
+void cp_default_options(cp_options *o);
+
+/*
+ * xi(r) auto-count of d (Section 1.1 eqn:separations, first case).
+ *   edges   nedges >= 2 host doubles, finite, strictly increasing, edges[0] >= 0
+ *   npairs  nedges-1 host uint64 counts (required)
+ *   wsum, ravg  nedges-1 host doubles each, written when need_ravg (then required)
+ * Fewer than two points give zero counts and CP_OK.
+ */
+int countpairs_xi(const cp_points *d, const double *edges, int nedges,
+                  const cp_options *o, uint64_t *npairs, double *wsum,
+                  double *ravg);
+
+/*
+ * wp auto-count: 2-D histogram xi(rp, pi) (Section 1.1 eqn:separations,
+ * second case; pi_max filter), line of sight z.
+ *   rp_edges  as edges above, bins in rp
+ *   pimax     > 0; npibins >= 1 equal pi bins in [0, pimax)
+ *   npairs    (nedges-1) * npibins host uint64, rp-major
+ *   wsum, rpavg  same shape, when need_ravg
+ */
+int countpairs_wp(const cp_points *d, const double *rp_edges, int nedges,
+                  double pimax, int npibins, const cp_options *o,
+                  uint64_t *npairs, double *wsum, double *rpavg);
+
+/*
+ * xi(r) cross-count: every ordered pair (i in d1, j in d2) (Section 1.1: the
+ * DR and RR terms of survey geometries; Section 2.1: no symmetry for cross
+ * correlations).  count_mode is ignored.  Pair weight w1_i * w2_j.
+ */
+int countpairs_cross(const cp_points *d1, const cp_points *d2,
+                     const double *edges, int nedges, const cp_options *o,
+                     uint64_t *npairs, double *wsum, double *ravg);
+
+/* wp cross-count (same conventions as countpairs_wp and countpairs_cross). */
+int countpairs_cross_wp(const cp_points *d1, const cp_points *d2,
+                        const double *rp_edges, int nedges, double pimax,
+                        int npibins, const cp_options *o, uint64_t *npairs,
+                        double *wsum, double *rpavg);
+
+/* Device scratch (bytes) a call on n1 (+ n2 for cross) points needs at most,
+ * for a caller-supplied workspace.  kind: 0 xi, 1 wp, 2 cross, 3 cross_wp. */
+size_t countpairs_workspace_size(int kind, int64_t n1, int64_t n2,
+                                 const double *edges, int nedges, double pimax,
+                                 int npibins, const cp_options *o);
+
+const char *countpairs_strerror(int code);
+const char *countpairs_last_error(void);
+int countpairs_last_stats(cp_stats *out);
+
+/*
+ * Batched plan: many catalogues of uneven size counted together (Section 1.1
+ * motivates many correlation-function evaluations, e.g. inside MCMC).  All
+ * catalogues share the periodic box, the bins and the precision.  One
+ * execute enqueues, on one stream, the cell build of every catalogue and one
+ * persistent pair launch for xi and one for wp that drain a shared queue of
+ * tiles ordered by decreasing cost.  Execute allocates nothing and is safe
+ * to capture in a hipGraph; the plan owns all scratch memory.
+ *
+ *   cp_plan_create   mocks: nmocks point sets (device pointers read at every
+ *                    execute, so the caller may refill them in place);
+ *                    xi_edges / wp_edges may be NULL to skip that statistic;
+ *                    o: precision, refine, periodic (must be 1) and boxsize.
+ *   cp_plan_execute  enqueue one evaluation on stream (asynchronous).
+ *   cp_plan_results  synchronise and copy counts: xi_npairs nmocks*(xi_nedges-1),
+ *                    wp_npairs nmocks*(wp_nedges-1)*npibins (either may be NULL);
+ *                    auto-counts follow o->count_mode.
+ *   cp_plan_destroy  free everything (NULL is fine).
+ */
+typedef struct cp_plan cp_plan;
+
+int cp_plan_create(const cp_points *mocks, int nmocks, const double *xi_edges,
+                   int xi_nedges, const double *wp_edges, int wp_nedges,
+                   double pimax, int npibins, const cp_options *o,
+                   cp_plan **out);
+int cp_plan_execute(cp_plan *plan, void *stream);
+int cp_plan_results(cp_plan *plan, uint64_t *xi_npairs, uint64_t *wp_npairs);
+int cp_plan_stats(cp_plan *plan, cp_stats *xi_stats, cp_stats *wp_stats);
+int cp_plan_destroy(cp_plan *plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* COUNTPAIRS_H */

@@ -1,0 +1,62 @@
+"""Build step for the HIP library (libcountpairs.so, gfx950) - run by
+__graft_entry__.build() and usable as `python -m paper_1911_08275_amd.build`."""
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+LIB = os.path.join(HERE, "libcountpairs.so")
+SOURCES = ["api.hip", "grid_kernels.hip", "pair_kernels.hip"]
+
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+FLAGS = [
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    # binary64 separations must follow the reference operation sequence:
+    # no multiply-add contraction anywhere (binary32 FMAs are explicit)
+    "-ffp-contract=off",
+    # packed binary32 arithmetic stays off on this hardware
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-munsafe-fp-atomics",
+    "-Wno-unused-result",
+]
+
+
+def build(verbose: bool = False, jobs: int = 3) -> str:
+    srcs = [os.path.join(CSRC, s) for s in SOURCES]
+    objs = [os.path.join(CSRC, s.replace(".hip", ".o")) for s in SOURCES]
+    procs = []
+    for src, obj in zip(srcs, objs):
+        cmd = [HIPCC] + [f for f in FLAGS if f != "-shared"] + ["-c", src, "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append(subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT))
+    failed = []
+    for p, src in zip(procs, srcs):
+        out, _ = p.communicate()
+        text = out.decode(errors="replace")
+        text = "\n".join(l for l in text.splitlines() if "packed-fp32-ops" not in l)
+        if p.returncode != 0:
+            failed.append((src, text))
+        elif verbose and text.strip():
+            print(text)
+    if failed:
+        for src, text in failed:
+            sys.stderr.write(f"--- {src}\n{text}\n")
+        raise RuntimeError("hipcc failed")
+    tmp = LIB + f".tmp{os.getpid()}"
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
+    subprocess.check_call(cmd)
+    os.replace(tmp, LIB)
+    for o in objs:
+        try:
+            os.remove(o)
+        except OSError:
+            pass
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose=True))

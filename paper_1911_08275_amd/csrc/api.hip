@@ -1,0 +1,1374 @@
+// Host side of libcountpairs: argument checks, grid geometry, the binary32
+// error bound and decision tables, device scratch, kernel launches and the
+// C ABI declared in include/countpairs.h.
+#include "cp_internal.h"
+#include "../../include/countpairs.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cfloat>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+namespace cp {
+
+// kernels (grid_kernels.hip, pair_kernels.hip)
+__global__ void k_bbox_partial(PointsDev a, PointsDev b, double *out, int *err);
+__global__ void k_bbox_final(const double *part, int nblk, double *out);
+__global__ void k_fill_i32(int *p, int64_t n, int v);
+__global__ void k_fill_u64(unsigned long long *p, int64_t n);
+__global__ void k_fill_f64(double *p, int64_t n);
+struct ScanSeg {
+  int64_t in_off;
+  int64_t out_off;
+  int64_t len;
+};
+__global__ void k_scan_segments(const int *in, int *out, const ScanSeg *segs);
+__global__ void k_assign(const PointsDev *pts, const GridGeom *geom, int *cell_count, int *cid,
+                         int *rank, int *err);
+__global__ void k_scatter(const PointsDev *pts, const GridGeom *geom, const int *cstart,
+                          const int *cid, const int *rank, double4 *pos, float4 *strm, int mode);
+__global__ void k_cellbox(const GridGeom *geom, int nmock, const int *cstart, const double4 *pos,
+                          CellBox *cbox, const int64_t *cell_prefix);
+__global__ void k_tiles(const GridGeom *geom, int nmock, const int *cstart, const int *maxspan,
+                        const int64_t *col_prefix, int *colcnt, const int *coloff, Tile *tiles,
+                        int emit);
+template <int MODE, int PREC, int W> __global__ void k_pairs(PairParams P);
+
+struct LdsLayout {
+  size_t tab32, tab64, E, common, wave_hist, wave_w, wave_bytes;
+};
+static size_t align16h(size_t v) { return (v + 15) & ~(size_t)15; }
+// identical to the device-side layout in pair_kernels.hip
+static LdsLayout lds_layout_host(int mode, int prec, int weighted, int n32, int n64, int nb,
+                                 int npi) {
+  LdsLayout L;
+  size_t off = 0;
+  L.tab32 = off;
+  off += (size_t)(prec == F32R ? n32 : 0) * 8;
+  L.tab64 = off;
+  off += (size_t)n64 * 8;
+  L.E = off;
+  off += (size_t)(nb + 1) * 8;
+  L.common = align16h(off);
+  const int NS = nb + 2;
+  const size_t words = mode == XI ? (size_t)NS * 64 : (size_t)NS * npi;
+  L.wave_hist = align16h(words * 4);
+  L.wave_w = weighted ? words * 8 : 0;
+  L.wave_bytes = L.wave_hist + 2 * L.wave_w;
+  return L;
+}
+
+// ------------------------------------------------------------ error state
+
+static thread_local std::string g_err;
+static thread_local cp_stats g_stats;
+static thread_local bool g_stats_valid = false;
+
+static int fail(int code, const std::string &msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIPCHK(expr)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(CP_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));   \
+  } while (0)
+
+// --------------------------------------------------------- rounding helpers
+
+static float f32_down(double x) {
+  float f = (float)x;
+  if ((double)f > x) f = std::nextafter(f, -INFINITY);
+  return f;
+}
+static float f32_up(double x) {
+  float f = (float)x;
+  if ((double)f < x) f = std::nextafter(f, INFINITY);
+  return f;
+}
+static uint32_t fbits(float f) {
+  uint32_t b;
+  memcpy(&b, &f, 4);
+  return b;
+}
+static float bitsf(uint32_t b) {
+  float f;
+  memcpy(&f, &b, 4);
+  return f;
+}
+
+// ----------------------------------------------------------- decision table
+//
+// Each edge E_k has an uncertain band [C_k, A_k) of binary32 estimates v:
+// v < C_k proves s < E_k and v >= A_k proves s >= E_k.  The table is indexed
+// by (bits(v) >> shift) clamped to [lo, hi]; entry = (t_lo, t_hi | kup):
+//   slot = kup - 1 + (v >= t_hi),  uncertain = (v >= t_lo) && !(v >= t_hi),
+// where slot counts the edges certainly below v (0 = below E_0, nb + 1 =
+// at or above E_nb).  A cell holding more than one band boundary is marked
+// uncertain as a whole, which is always safe.
+
+struct Table {
+  std::vector<uint2> e;
+  int lo = 0, hi = 0;
+};
+
+static const uint32_t kBig = 0x7E000000u;     // ~4.25e37, finite
+static const float kNegBig = -3.0e38f;
+
+static uint32_t hi_with_k(float z, int k) {
+  uint32_t b = fbits(z);
+  uint32_t b2 = (b & ~63u) | (uint32_t)k;
+  if (b2 < b) b2 += 64;
+  return b2;
+}
+
+static bool build_table(const std::vector<float> &C, const std::vector<float> &Av, int shift,
+                        Table &T) {
+  const int nt = (int)C.size();  // nb + 1 thresholds
+  // merged uncertain zones
+  struct Z {
+    float lo, hi;
+  };
+  std::vector<Z> zones;
+  for (int k = 0; k < nt; k++) {
+    if (!(Av[k] > C[k])) continue;
+    if (!zones.empty() && C[k] <= zones.back().hi)
+      zones.back().hi = std::max(zones.back().hi, Av[k]);
+    else
+      zones.push_back({C[k], Av[k]});
+  }
+  auto sigma = [&](float v) {
+    int s = 0;
+    for (int k = 0; k < nt; k++) s += (Av[k] <= v);
+    return s;
+  };
+  auto cell_of = [&](float v) { return (int)((int32_t)fbits(v) >> shift); };
+  float minpos = INFINITY;
+  for (int k = 0; k < nt; k++) {
+    if (C[k] > 0) minpos = std::min(minpos, C[k]);
+    if (Av[k] > 0) minpos = std::min(minpos, Av[k]);
+  }
+  if (!std::isfinite(minpos)) minpos = Av[nt - 1];
+  T.lo = cell_of(minpos);
+  T.hi = std::max(T.lo, cell_of(Av[nt - 1]));
+  if (T.hi - T.lo + 1 > 4096) return false;
+  T.e.assign(T.hi - T.lo + 1, make_uint2(0, 0));
+  for (int m = T.lo; m <= T.hi; m++) {
+    const float vlo = m == T.lo ? -INFINITY : bitsf((uint32_t)m << shift);
+    const float vhi = m == T.hi ? INFINITY : bitsf((uint32_t)(m + 1) << shift);
+    std::vector<Z> in;
+    for (const Z &z : zones)
+      if (z.hi > vlo && z.lo < vhi) in.push_back(z);
+    uint2 ent;
+    const uint2 all_unc = make_uint2(fbits(kNegBig), kBig | 1u);
+    if (in.empty()) {
+      const float rep = m == T.lo ? bitsf((uint32_t)m << shift) : vlo;
+      const int s = sigma(rep);
+      ent = make_uint2(kBig, kBig | (uint32_t)(s + 1));
+    } else if (in.size() > 1) {
+      ent = all_unc;
+    } else {
+      const Z z = in[0];
+      const bool sin = z.lo > vlo, ein = z.hi < vhi;
+      if (!sin && !ein) {
+        ent = all_unc;
+      } else if (!sin && ein) {
+        const int sh = sigma(z.hi);
+        ent = make_uint2(fbits(kNegBig), hi_with_k(z.hi, sh));
+      } else if (sin && !ein) {
+        const int sl = sigma(std::nextafter(z.lo, -INFINITY));
+        ent = make_uint2(fbits(z.lo), kBig | (uint32_t)(sl + 1));
+      } else {
+        const int sl = sigma(std::nextafter(z.lo, -INFINITY));
+        const int sh = sigma(z.hi);
+        if (sh == sl + 1)
+          ent = make_uint2(fbits(z.lo), hi_with_k(z.hi, sh));
+        else
+          ent = all_unc;
+      }
+    }
+    T.e[m - T.lo] = ent;
+  }
+  return true;
+}
+
+// ---------------------------------------------------------------- geometry
+
+struct Geometry {
+  int n[3], r[3], wrap[3];
+  double lo[3], cs[3], ext[3];
+  int maxspan;
+  bool ok;
+};
+
+static Geometry choose_geometry(int mode, bool periodic, double box, const double lo[3],
+                                const double ext[3], double rmax, double pimax,
+                                const int refine_in[3], int64_t npts_total) {
+  Geometry g;
+  const double reach[3] = {rmax, rmax, mode == XI ? rmax : pimax};
+  int refine[3];
+  for (int a = 0; a < 3; a++) {
+    int dflt = a < 2 ? 2 : 1;
+    refine[a] = refine_in && refine_in[a] > 0 ? refine_in[a] : dflt;
+    if (refine[a] > 8) refine[a] = 8;
+  }
+  for (int a = 0; a < 3; a++) {
+    g.lo[a] = periodic ? 0.0 : lo[a];
+    g.ext[a] = periodic ? box : ext[a];
+    g.wrap[a] = 0;
+    int ref = refine[a];
+    int n = 1;
+    if (g.ext[a] > 0) {
+      for (;;) {
+        double f = std::floor(g.ext[a] / (reach[a] / ref * (1.0 + 1e-9)));
+        n = f < 1 ? 1 : (f > kMaxAxisCells ? kMaxAxisCells : (int)f);
+        if (!periodic || ref <= 1 || n >= 2 * ref + 1) break;
+        ref--;
+      }
+    }
+    if (periodic && n < 2 * ref + 1) {
+      // fewer than three cells per reach: one cell, per-pair minimum image
+      n = 1;
+      ref = 0;
+      g.wrap[a] = 1;
+    }
+    if (!periodic && n == 1) ref = 0;
+    g.n[a] = n;
+    g.r[a] = ref;
+  }
+  // bound the cell count by the points (sparse data): coarsen the finest axis
+  const int64_t cap = std::max<int64_t>(4096, 4 * npts_total);
+  while ((int64_t)g.n[0] * g.n[1] * g.n[2] > cap) {
+    int a = 0;
+    for (int b = 1; b < 3; b++)
+      if (g.n[b] > g.n[a]) a = b;
+    int nn = std::max(1, (int)(g.n[a] * 0.8));
+    if (periodic && nn < 2 * g.r[a] + 1) {
+      // keep the no-aliasing condition: drop to one wrapped cell
+      nn = 1;
+      g.r[a] = 0;
+      g.wrap[a] = 1;
+    }
+    if (!periodic && nn == 1) g.r[a] = 0;
+    g.n[a] = nn;
+  }
+  for (int a = 0; a < 3; a++) g.cs[a] = g.ext[a] > 0 ? g.ext[a] / g.n[a] : 1.0;
+  int span = std::max(2, 2 * g.r[2]);
+  if (periodic && !g.wrap[2]) span = std::min(span, g.n[2] - 2 * g.r[2]);
+  g.maxspan = std::max(1, span);
+  g.ok = true;
+  return g;
+}
+
+static GridGeom to_dev_geom(const Geometry &g, bool periodic, double box, int64_t pbase,
+                            int64_t cbase, int64_t sbase, int64_t npts, int64_t colbase) {
+  GridGeom G;
+  memset(&G, 0, sizeof(G));
+  for (int a = 0; a < 3; a++) {
+    G.n[a] = g.n[a];
+    G.r[a] = g.r[a];
+    G.wrap[a] = g.wrap[a];
+    G.lo[a] = g.lo[a];
+    G.cs[a] = g.cs[a];
+    G.inv[a] = 1.0 / g.cs[a];
+  }
+  G.periodic = periodic ? 1 : 0;
+  G.box = periodic ? box : 0.0;
+  G.halfbox = 0.5 * G.box;
+  G.pbase = pbase;
+  G.cbase = cbase;
+  G.sbase = sbase;
+  G.npts = npts;
+  G.ncell = g.n[0] * g.n[1] * g.n[2];
+  G.ncol = g.n[0] * g.n[1];
+  G.colbase = colbase;
+  return G;
+}
+
+// ------------------------------------------------------ binary32 error bound
+
+struct Bounds {
+  double eps;        // |s~ - s| bound for the squared (projected) separation
+  double eta_pi;     // |pi~ - pi| bound (wp)
+};
+
+static Bounds error_bounds(int mode, const Geometry &g, double EB, double pimax, double M) {
+  const double u = std::ldexp(1.0, -24), u64 = std::ldexp(1.0, -53);
+  const double eB = std::sqrt(EB);
+  Bounds b;
+  if (mode == XI) {
+    const double P =
+        0.5 * std::sqrt(g.cs[0] * g.cs[0] + g.cs[1] * g.cs[1] + g.cs[2] * g.cs[2]) * (1 + 1e-6);
+    const double G = 2 * P + eB;
+    const double eta = u * G * 1.01 + 4 * std::sqrt(3.0) * u64 * M;
+    b.eps = 2.0 * (7.5 * u * G * G + 2 * eB * eta + eta * eta + 8 * u64 * (EB + 2 * eB * M));
+    b.eta_pi = 0;
+  } else {
+    const double P = 0.5 * std::sqrt(g.cs[0] * g.cs[0] + g.cs[1] * g.cs[1]) * (1 + 1e-6);
+    const double G = 2 * P + eB;
+    const double eta = u * G * 1.01 + 4 * std::sqrt(2.0) * u64 * M;
+    b.eps = 2.0 * (5.5 * u * G * G + 2 * eB * eta + eta * eta + 8 * u64 * (EB + 2 * eB * M));
+    const double Pz = 0.5 * g.cs[2] * (1 + 1e-6);
+    b.eta_pi = 2.0 * (u * (2 * Pz + 2 * pimax) * 1.01 + 4 * u64 * M);
+  }
+  return b;
+}
+
+// ----------------------------------------------------------- device arena
+
+struct Arena {
+  void *base = nullptr;
+  size_t cap = 0;
+};
+static thread_local Arena g_arena;
+
+struct Carver {
+  char *p;
+  size_t off = 0;
+  bool dry;
+  explicit Carver(void *b, bool d) : p((char *)b), dry(d) {}
+  template <class T> T *take(size_t n) {
+    off = (off + 255) & ~(size_t)255;
+    T *r = dry ? nullptr : (T *)(p + off);
+    off += n * sizeof(T);
+    return r;
+  }
+};
+
+// Device buffers of one gridded point set.
+struct SetBufs {
+  int *ccount, *cstart, *cid, *rank, *colcnt, *coloff;
+  double4 *pos;
+  float4 *strm;
+  CellBox *cbox;
+  Tile *tiles;
+};
+
+static void carve_set(Carver &cv, SetBufs &S, int64_t n, int64_t ncell, int64_t ncol,
+                      bool want_tiles, int64_t maxtiles) {
+  S.ccount = cv.take<int>(ncell);
+  S.cstart = cv.take<int>(ncell + 1);
+  S.cid = cv.take<int>(n > 0 ? n : 1);
+  S.rank = cv.take<int>(n > 0 ? n : 1);
+  S.pos = cv.take<double4>(n > 0 ? n : 1);
+  S.strm = cv.take<float4>(n > 0 ? n : 1);
+  S.cbox = cv.take<CellBox>(ncell);
+  if (want_tiles) {
+    S.colcnt = cv.take<int>(ncol + 1);
+    S.coloff = cv.take<int>(ncol + 1);
+    S.tiles = cv.take<Tile>(maxtiles);
+  } else {
+    S.colcnt = S.coloff = nullptr;
+    S.tiles = nullptr;
+  }
+}
+
+// Small per-call records uploaded in one copy.
+struct Smalls {
+  GridGeom geom[2];
+  PointsDev pts[2];
+  ScanSeg seg[3];
+  int64_t cell_prefix[2];
+  int64_t col_prefix[2];
+  int maxspan[2];
+  int ntiles_dummy;
+};
+
+struct Call {
+  int mode;          // XI / WP
+  bool cross;
+  const cp_points *d1, *d2;
+  const double *edges;
+  int nedges;
+  double pimax;
+  int npi;
+  const cp_options *o;
+};
+
+static int check_points(const cp_points *p, const char *name) {
+  if (!p) return fail(CP_ERR_INVALID_ARG, std::string(name) + " is NULL");
+  if (p->n < 0) return fail(CP_ERR_INVALID_ARG, std::string(name) + "->n < 0");
+  if (p->n > ((int64_t)1 << 31) - 1)
+    return fail(CP_ERR_INVALID_ARG, std::string(name) + "->n above 2^31 - 1");
+  if (p->dtype != CP_F64 && p->dtype != CP_F32)
+    return fail(CP_ERR_INVALID_ARG, std::string(name) + "->dtype must be CP_F64 or CP_F32");
+  if (p->n > 0 && (!p->x || !p->y || !p->z))
+    return fail(CP_ERR_INVALID_ARG, std::string(name) + " has NULL coordinates");
+  return CP_OK;
+}
+
+static int check_common(const Call &c) {
+  if (!c.o) return fail(CP_ERR_INVALID_ARG, "options is NULL");
+  const cp_options &o = *c.o;
+  if (!c.edges || c.nedges < 2) return fail(CP_ERR_INVALID_ARG, "need nedges >= 2 edges");
+  if (c.nedges - 1 > kMaxBins)
+    return fail(CP_ERR_INVALID_ARG, "at most " + std::to_string(kMaxBins) + " bins");
+  for (int k = 0; k < c.nedges; k++) {
+    if (!std::isfinite(c.edges[k])) return fail(CP_ERR_INVALID_ARG, "non-finite edge");
+    if (k > 0 && !(c.edges[k] > c.edges[k - 1]))
+      return fail(CP_ERR_INVALID_ARG, "edges must increase strictly");
+  }
+  if (c.edges[0] < 0) return fail(CP_ERR_INVALID_ARG, "edges[0] < 0");
+  if (c.mode == WP) {
+    if (!(c.pimax > 0) || !std::isfinite(c.pimax))
+      return fail(CP_ERR_INVALID_ARG, "pimax must be positive and finite");
+    if (c.npi < 1 || c.npi > kMaxPiBins)
+      return fail(CP_ERR_INVALID_ARG, "npibins must be in [1, " + std::to_string(kMaxPiBins) + "]");
+  }
+  if (o.precision != CP_PREC_FP64 && o.precision != CP_PREC_FP32_RECHECK)
+    return fail(CP_ERR_INVALID_ARG, "bad precision");
+  if (o.count_mode != CP_ORDERED && o.count_mode != CP_UNIQUE)
+    return fail(CP_ERR_INVALID_ARG, "bad count_mode");
+  if (o.periodic && (!(o.boxsize > 0) || !std::isfinite(o.boxsize)))
+    return fail(CP_ERR_INVALID_ARG, "periodic needs a positive finite boxsize");
+  for (int a = 0; a < 3; a++)
+    if (o.refine[a] < 0) return fail(CP_ERR_INVALID_ARG, "refine must be >= 0");
+  if (o.workspace && !o.workspace_bytes)
+    return fail(CP_ERR_INVALID_ARG, "workspace given with zero size");
+  return CP_OK;
+}
+
+static int64_t max_tiles_bound(int64_t n, int64_t ncell, int64_t ncol) {
+  return ncell + n / kTileMax + ncol + 1;
+}
+
+// Launch the cell build of one point set (cell counts .. tiles).
+static int launch_build(hipStream_t st, const PointsDev *d_pts, const GridGeom *d_geom,
+                        const SetBufs &S, int64_t n, int64_t ncell, int64_t ncol, int mode,
+                        const ScanSeg *d_seg_cells, const ScanSeg *d_seg_cols,
+                        const int64_t *d_cell_prefix, const int64_t *d_col_prefix,
+                        const int *d_maxspan, int *d_err, bool tiles) {
+  const int fb = (int)std::min<int64_t>(std::max<int64_t>((ncell + 255) / 256, 1), 4096);
+  hipLaunchKernelGGL(k_fill_i32, dim3(fb), dim3(256), 0, st, S.ccount, ncell, 0);
+  const int ab = (int)std::min<int64_t>(std::max<int64_t>((n + 255) / 256, 1), 8192);
+  if (n > 0)
+    hipLaunchKernelGGL(k_assign, dim3(ab, 1), dim3(256), 0, st, d_pts, d_geom, S.ccount, S.cid,
+                       S.rank, d_err);
+  hipLaunchKernelGGL(k_scan_segments, dim3(1), dim3(1024), 0, st, S.ccount, S.cstart,
+                     d_seg_cells);
+  if (n > 0)
+    hipLaunchKernelGGL(k_scatter, dim3(ab, 1), dim3(256), 0, st, d_pts, d_geom, S.cstart, S.cid,
+                       S.rank, S.pos, S.strm, mode);
+  const int cb = (int)std::min<int64_t>(std::max<int64_t>((ncell + 3) / 4, 1), 16384);
+  hipLaunchKernelGGL(k_cellbox, dim3(cb), dim3(256), 0, st, d_geom, 1, S.cstart, S.pos, S.cbox,
+                     d_cell_prefix);
+  if (tiles) {
+    const int tb = (int)std::max<int64_t>((ncol + 255) / 256, 1);
+    hipLaunchKernelGGL(k_tiles, dim3(tb), dim3(256), 0, st, d_geom, 1, S.cstart, d_maxspan,
+                       d_col_prefix, S.colcnt, S.coloff, S.tiles, 0);
+    hipLaunchKernelGGL(k_scan_segments, dim3(1), dim3(1024), 0, st, S.colcnt, S.coloff,
+                       d_seg_cols);
+    hipLaunchKernelGGL(k_tiles, dim3(tb), dim3(256), 0, st, d_geom, 1, S.cstart, d_maxspan,
+                       d_col_prefix, S.colcnt, S.coloff, S.tiles, 1);
+  }
+  return hipGetLastError() == hipSuccess ? CP_OK : fail(CP_ERR_DEVICE, "cell build launch failed");
+}
+
+static int g_num_cus = 0;
+static int num_cus() {
+  if (!g_num_cus) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    hipDeviceProp_t p;
+    if (hipGetDeviceProperties(&p, dev) == hipSuccess) g_num_cus = p.multiProcessorCount;
+    if (g_num_cus <= 0) g_num_cus = 256;
+  }
+  return g_num_cus;
+}
+
+template <int MODE, int PREC, int W>
+static int launch_pairs_t(hipStream_t st, const PairParams &P, size_t lds, int nwaves) {
+  auto kern = k_pairs<MODE, PREC, W>;
+  static thread_local size_t set_lds = 0;
+  if (lds > 65536 && lds > set_lds) {
+    if (hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds) != hipSuccess)
+      return fail(CP_ERR_DEVICE, "cannot raise the LDS limit of the pair kernel");
+    set_lds = lds;
+  }
+  const int per_cu = std::max(1, std::min(8, (int)(160 * 1024 / std::max<size_t>(lds, 1))));
+  const int grid = num_cus() * per_cu;
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * nwaves), lds, st, P);
+  return hipGetLastError() == hipSuccess ? CP_OK : fail(CP_ERR_DEVICE, "pair launch failed");
+}
+
+static int launch_pairs(hipStream_t st, int mode, int prec, int w, const PairParams &P,
+                        size_t lds, int nwaves) {
+  if (mode == XI) {
+    if (prec == F32R) return w ? launch_pairs_t<XI, F32R, 1>(st, P, lds, nwaves)
+                               : launch_pairs_t<XI, F32R, 0>(st, P, lds, nwaves);
+    return w ? launch_pairs_t<XI, F64, 1>(st, P, lds, nwaves)
+             : launch_pairs_t<XI, F64, 0>(st, P, lds, nwaves);
+  }
+  if (prec == F32R) return w ? launch_pairs_t<WP, F32R, 1>(st, P, lds, nwaves)
+                             : launch_pairs_t<WP, F32R, 0>(st, P, lds, nwaves);
+  return w ? launch_pairs_t<WP, F64, 1>(st, P, lds, nwaves)
+           : launch_pairs_t<WP, F64, 0>(st, P, lds, nwaves);
+}
+
+// Binning setup shared by single calls and plans.
+struct Binning {
+  std::vector<double> E;
+  Table t32, t64;
+  int shift;
+  float AB32;
+  Bounds bnd;
+  float inv_dpi32, pi_delta, pi_lo32, pi_hi32;
+  double dpi;
+};
+
+static int make_binning(int mode, int prec, const double *edges, int nedges, double pimax,
+                        int npi, const Geometry &g, double M, Binning &B) {
+  const int nb = nedges - 1;
+  B.E.resize(nedges);
+  for (int k = 0; k < nedges; k++) B.E[k] = edges[k] * edges[k];
+  const double EB = B.E[nb];
+  B.bnd = error_bounds(mode, g, EB, pimax, M);
+  std::vector<float> C32(nedges), A32(nedges), C64(nedges), A64(nedges);
+  for (int k = 0; k < nedges; k++) {
+    const double e = B.E[k];
+    if (e == 0.0) {
+      C32[k] = A32[k] = C64[k] = A64[k] = -FLT_MAX;   // s >= 0 = E_0 always
+      continue;
+    }
+    C32[k] = f32_down(e - B.bnd.eps);
+    A32[k] = f32_up(e + B.bnd.eps);
+    C64[k] = f32_down(e * (1.0 - std::ldexp(1.0, -22)));
+    A64[k] = f32_up(e * (1.0 + std::ldexp(1.0, -22)));
+  }
+  for (int shift = 18; shift <= 23; shift++) {
+    bool ok = build_table(C64, A64, shift, B.t64);
+    if (ok && prec == F32R) ok = build_table(C32, A32, shift, B.t32);
+    if (ok) {
+      B.shift = shift;
+      break;
+    }
+    if (shift == 23) return fail(CP_ERR_INVALID_ARG, "edges span too many octaves");
+  }
+  if (prec != F32R) B.t32 = B.t64;
+  B.AB32 = A32[nb];
+  B.dpi = mode == WP ? pimax / npi : 1.0;
+  if (mode == WP) {
+    const double u = std::ldexp(1.0, -24);
+    B.inv_dpi32 = (float)(1.0 / B.dpi);
+    B.pi_delta = (float)(B.bnd.eta_pi / B.dpi + 3 * u * npi + 1e-12 * npi);
+    B.pi_lo32 = f32_down(pimax - B.bnd.eta_pi);
+    B.pi_hi32 = f32_up(pimax + B.bnd.eta_pi);
+  } else {
+    B.inv_dpi32 = 1.0f;
+    B.pi_delta = 0.f;
+    B.pi_lo32 = B.pi_hi32 = 0.f;
+  }
+  return CP_OK;
+}
+
+static int map_err_flags(int flags) {
+  if (flags & 1) return fail(CP_ERR_NONFINITE, "non-finite coordinate or weight");
+  if (flags & 2) return fail(CP_ERR_OUT_OF_BOX, "periodic coordinate outside [0, boxsize)");
+  return CP_OK;
+}
+
+// ------------------------------------------------------------- single call
+
+static int run(const Call &c, uint64_t *npairs, double *wsum, double *ravg) {
+  int rc = check_common(c);
+  if (rc) return rc;
+  if ((rc = check_points(c.d1, c.cross ? "d1" : "d"))) return rc;
+  if (c.cross && (rc = check_points(c.d2, "d2"))) return rc;
+  if (!npairs) return fail(CP_ERR_INVALID_ARG, "npairs is NULL");
+  const cp_options &o = *c.o;
+  if (o.need_ravg && (!wsum || !ravg))
+    return fail(CP_ERR_INVALID_ARG, "need_ravg with NULL wsum or ravg");
+  const int nb = c.nedges - 1;
+  const int npi = c.mode == WP ? c.npi : 1;
+  const int nout = nb * npi;
+  const bool autoc = !c.cross;
+  const cp_points &p1 = *c.d1;
+  const cp_points &p2 = autoc ? *c.d1 : *c.d2;
+  hipStream_t st = (hipStream_t)o.stream;
+  g_stats_valid = false;
+  memset(npairs, 0, sizeof(uint64_t) * nout);
+  if (o.need_ravg) {
+    memset(wsum, 0, sizeof(double) * nout);
+    memset(ravg, 0, sizeof(double) * nout);
+  }
+  if (p1.n + (autoc ? 0 : p2.n) == 0) {
+    memset(&g_stats, 0, sizeof(g_stats));
+    g_stats_valid = true;
+    return CP_OK;
+  }
+  const bool weighted = o.need_ravg != 0;
+  const double rmax = c.edges[nb];
+
+  hipEvent_t ev[4];
+  for (auto &e : ev) HIPCHK(hipEventCreate(&e));
+  struct EvGuard {
+    hipEvent_t *e;
+    ~EvGuard() {
+      for (int i = 0; i < 4; i++) (void)hipEventDestroy(e[i]);
+    }
+  } evg{ev};
+  HIPCHK(hipEventRecord(ev[0], st));
+
+  PointsDev pd[2];
+  auto fillpd = [](const cp_points &p, PointsDev &d) {
+    d.x = p.x;
+    d.y = p.y;
+    d.z = p.z;
+    d.w = p.w;
+    d.n = p.n;
+    d.dtype = p.dtype;
+    d.pad = 0;
+  };
+  fillpd(p1, pd[0]);
+  fillpd(p2, pd[1]);
+
+  // ---- domain
+  double lo[3] = {0, 0, 0}, ext[3] = {0, 0, 0};
+  int *d_err0 = nullptr;
+  if (!o.periodic) {
+    // joint bounding box (Section 2.1: computed first) - needs a round trip
+    double *d_part = nullptr;
+    const int nblk = 256;
+    HIPCHK(hipMallocAsync((void **)&d_part, sizeof(double) * (6 * nblk + 6) + 16, st));
+    d_err0 = (int *)(d_part + 6 * nblk + 6);
+    HIPCHK(hipMemsetAsync(d_err0, 0, sizeof(int), st));
+    PointsDev b = pd[1];
+    if (autoc) b.n = 0;
+    hipLaunchKernelGGL(k_bbox_partial, dim3(nblk), dim3(256), 0, st, pd[0], b, d_part, d_err0);
+    hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(64), 0, st, d_part, nblk, d_part + 6 * nblk);
+    double bb[6];
+    int eflag = 0;
+    HIPCHK(hipMemcpyAsync(bb, d_part + 6 * nblk, sizeof(bb), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(&eflag, d_err0, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    HIPCHK(hipFreeAsync(d_part, st));
+    if ((rc = map_err_flags(eflag))) return rc;
+    for (int a = 0; a < 3; a++) {
+      lo[a] = bb[a];
+      ext[a] = bb[a + 3] - bb[a];
+      if (!(ext[a] >= 0)) {
+        lo[a] = 0;
+        ext[a] = 0;
+      }
+    }
+  }
+  const int64_t ntot = p1.n + (autoc ? 0 : p2.n);
+  Geometry g = choose_geometry(c.mode, o.periodic != 0, o.boxsize, lo, ext, rmax, c.pimax,
+                               o.refine, ntot);
+  int prec = o.precision == CP_PREC_FP32_RECHECK ? F32R : F64;
+  if (g.wrap[0] || g.wrap[1] || g.wrap[2]) prec = F64;   // per-pair minimum image: binary64
+  double M = 0;
+  for (int a = 0; a < 3; a++) M = std::max(M, std::fabs(g.lo[a]) + g.ext[a]);
+  if (o.periodic) M = std::max(M, o.boxsize);
+  Binning B;
+  if ((rc = make_binning(c.mode, prec, c.edges, c.nedges, c.pimax, npi, g, M, B))) return rc;
+
+  const int64_t ncell = (int64_t)g.n[0] * g.n[1] * g.n[2];
+  const int64_t ncol = (int64_t)g.n[0] * g.n[1];
+  const int64_t maxt = max_tiles_bound(p1.n, ncell, ncol);
+  const int n32 = (int)B.t32.e.size(), n64 = (int)B.t64.e.size();
+
+  // ---- scratch layout
+  auto layout = [&](Carver &cv, SetBufs &S1, SetBufs &S2, Smalls *&sm, uint2 *&t32, uint2 *&t64,
+                    double *&E, unsigned long long *&hist, double *&hw, double *&hwr,
+                    unsigned long long *&stats, unsigned long long *&qhead, int *&err) {
+    carve_set(cv, S1, p1.n, ncell, ncol, true, maxt);
+    if (!autoc) carve_set(cv, S2, p2.n, ncell, ncol, false, 0);
+    sm = cv.take<Smalls>(1);
+    t32 = cv.take<uint2>(n32);
+    t64 = cv.take<uint2>(n64);
+    E = cv.take<double>(c.nedges);
+    hist = cv.take<unsigned long long>(nout);
+    hw = cv.take<double>(nout);
+    hwr = cv.take<double>(nout);
+    stats = cv.take<unsigned long long>(5);   // 4 counters + queue head
+    qhead = stats + 4;
+    err = cv.take<int>(1);
+  };
+  SetBufs S1, S2;
+  Smalls *d_sm;
+  uint2 *d_t32, *d_t64;
+  double *d_E, *d_hw, *d_hwr;
+  unsigned long long *d_hist, *d_stats, *d_qhead;
+  int *d_err;
+  {
+    Carver dry(nullptr, true);
+    layout(dry, S1, S2, d_sm, d_t32, d_t64, d_E, d_hist, d_hw, d_hwr, d_stats, d_qhead, d_err);
+    const size_t need = dry.off + 256;
+    void *base;
+    if (o.workspace) {
+      if (o.workspace_bytes < need)
+        return fail(CP_ERR_NOMEM, "workspace too small: need " + std::to_string(need) + " bytes");
+      base = o.workspace;
+    } else {
+      if (g_arena.cap < need) {
+        if (g_arena.base) {
+          HIPCHK(hipDeviceSynchronize());
+          (void)hipFree(g_arena.base);
+          g_arena.base = nullptr;
+          g_arena.cap = 0;
+        }
+        size_t want = need + need / 4;
+        if (hipMalloc(&g_arena.base, want) != hipSuccess) {
+          g_arena.base = nullptr;
+          return fail(CP_ERR_NOMEM, "hipMalloc of " + std::to_string(want) + " bytes failed");
+        }
+        g_arena.cap = want;
+      }
+      base = g_arena.base;
+    }
+    Carver cv(base, false);
+    layout(cv, S1, S2, d_sm, d_t32, d_t64, d_E, d_hist, d_hw, d_hwr, d_stats, d_qhead, d_err);
+  }
+  if (autoc) S2 = S1;
+
+  // ---- small records
+  Smalls hs;
+  memset(&hs, 0, sizeof(hs));
+  hs.geom[0] = to_dev_geom(g, o.periodic != 0, o.boxsize, 0, 0, 0, p1.n, 0);
+  hs.geom[1] = to_dev_geom(g, o.periodic != 0, o.boxsize, 0, 0, 0, p2.n, 0);
+  hs.pts[0] = pd[0];
+  hs.pts[1] = pd[1];
+  hs.seg[0] = {0, 0, ncell};
+  hs.seg[1] = {0, 0, ncol};
+  hs.cell_prefix[0] = 0;
+  hs.cell_prefix[1] = ncell;
+  hs.col_prefix[0] = 0;
+  hs.col_prefix[1] = ncol;
+  hs.maxspan[0] = g.maxspan;
+  HIPCHK(hipMemcpyAsync(d_sm, &hs, sizeof(hs), hipMemcpyHostToDevice, st));
+  if (n32) HIPCHK(hipMemcpyAsync(d_t32, B.t32.e.data(), n32 * 8, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(d_t64, B.t64.e.data(), n64 * 8, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(d_E, B.E.data(), c.nedges * 8, hipMemcpyHostToDevice, st));
+  hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(256), 0, st, d_hist, (int64_t)nout);
+  hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(256), 0, st, d_hw, (int64_t)nout);
+  hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(256), 0, st, d_hwr, (int64_t)nout);
+  hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, d_stats, (int64_t)5);  // stats + qhead
+  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, d_err, (int64_t)1, 0);
+
+  // ---- cell build
+  rc = launch_build(st, &d_sm->pts[0], &d_sm->geom[0], S1, p1.n, ncell, ncol, c.mode,
+                    &d_sm->seg[0], &d_sm->seg[1], d_sm->cell_prefix, d_sm->col_prefix,
+                    d_sm->maxspan, d_err, true);
+  if (rc) return rc;
+  if (!autoc) {
+    rc = launch_build(st, &d_sm->pts[1], &d_sm->geom[1], S2, p2.n, ncell, ncol, c.mode,
+                      &d_sm->seg[0], &d_sm->seg[1], d_sm->cell_prefix, d_sm->col_prefix,
+                      d_sm->maxspan, d_err, false);
+    if (rc) return rc;
+  }
+  HIPCHK(hipEventRecord(ev[1], st));
+
+  // ---- pairs
+  PairParams P;
+  memset(&P, 0, sizeof(P));
+  P.tiles = S1.tiles;
+  P.ntiles = S1.coloff + ncol;
+  P.qhead = d_qhead;
+  P.geom1 = &d_sm->geom[0];
+  P.geom2 = &d_sm->geom[1];
+  P.pos1 = S1.pos;
+  P.pos2 = S2.pos;
+  P.strm2 = S2.strm;
+  P.cstart2 = S2.cstart;
+  P.cbox2 = S2.cbox;
+  P.tab32 = d_t32 ? d_t32 : d_t64;
+  P.tab64 = d_t64;
+  P.tab32_lo = B.t32.lo;
+  P.tab32_hi = B.t32.hi;
+  P.tab64_lo = B.t64.lo;
+  P.tab64_hi = B.t64.hi;
+  P.tab_shift = B.shift;
+  P.E = d_E;
+  P.nb = nb;
+  P.nslots = nb + 2;
+  P.AB32 = B.AB32;
+  P.EB = B.E[nb];
+  P.pimax = c.pimax;
+  P.dpi = B.dpi;
+  P.npi = npi;
+  P.inv_dpi32 = B.inv_dpi32;
+  P.pi_delta = B.pi_delta;
+  P.pi_lo32 = B.pi_lo32;
+  P.pi_hi32 = B.pi_hi32;
+  P.autocorr = autoc ? 1 : 0;
+  P.weighted = weighted ? 1 : 0;
+  P.hist = d_hist;
+  P.hw = d_hw;
+  P.hwr = d_hwr;
+  P.stats = d_stats;
+  P.hist_stride = nout;
+  const int nwaves = weighted && c.mode == XI ? 2 : 4;
+  const LdsLayout LY = lds_layout_host(c.mode, prec, weighted, n32, n64, nb, npi);
+  const size_t lds = LY.common + nwaves * LY.wave_bytes;
+  if (lds > 160 * 1024) return fail(CP_ERR_INVALID_ARG, "too many bins for the LDS budget");
+  if ((rc = launch_pairs(st, c.mode, prec, weighted, P, lds, nwaves))) return rc;
+  HIPCHK(hipEventRecord(ev[2], st));
+
+  // ---- results
+  std::vector<unsigned long long> h(nout);
+  std::vector<double> hwv(nout), hwrv(nout);
+  unsigned long long hst[5];
+  int eflag = 0;
+  int ntiles = 0;
+  HIPCHK(hipMemcpyAsync(h.data(), d_hist, 8 * nout, hipMemcpyDeviceToHost, st));
+  if (weighted) {
+    HIPCHK(hipMemcpyAsync(hwv.data(), d_hw, 8 * nout, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(hwrv.data(), d_hwr, 8 * nout, hipMemcpyDeviceToHost, st));
+  }
+  HIPCHK(hipMemcpyAsync(hst, d_stats, sizeof(hst), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(&eflag, d_err, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(&ntiles, S1.coloff + ncol, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipEventRecord(ev[3], st));
+  HIPCHK(hipStreamSynchronize(st));
+  if ((rc = map_err_flags(eflag))) return rc;
+  if (hst[4] < (unsigned long long)ntiles)
+    return fail(CP_ERR_INTERNAL, "work queue not drained");
+
+  const double mult = (autoc && o.count_mode == CP_ORDERED) ? 2.0 : 1.0;
+  for (int k = 0; k < nout; k++) {
+    npairs[k] = (uint64_t)h[k] * (uint64_t)mult;
+    if (weighted) {
+      wsum[k] = hwv[k] * mult;
+      ravg[k] = h[k] ? hwrv[k] / hwv[k] : 0.0;
+    }
+  }
+  memset(&g_stats, 0, sizeof(g_stats));
+  g_stats.candidates = hst[0];
+  g_stats.rechecks = hst[1];
+  g_stats.cell_pairs = hst[2];
+  g_stats.cell_pairs_pruned = hst[3];
+  g_stats.tiles = (uint64_t)ntiles;
+  for (int a = 0; a < 3; a++) {
+    g_stats.grid[a] = g.n[a];
+    g_stats.refine[a] = g.r[a];
+  }
+  (void)hipEventElapsedTime(&g_stats.ms_grid, ev[0], ev[1]);
+  (void)hipEventElapsedTime(&g_stats.ms_pairs, ev[1], ev[2]);
+  (void)hipEventElapsedTime(&g_stats.ms_total, ev[0], ev[3]);
+  g_stats_valid = true;
+  return CP_OK;
+}
+
+} // namespace cp
+
+// =================================================================== C ABI
+
+using namespace cp;
+
+extern "C" {
+
+void cp_default_options(cp_options *o) {
+  if (!o) return;
+  memset(o, 0, sizeof(*o));
+  o->precision = CP_PREC_FP32_RECHECK;
+  o->count_mode = CP_ORDERED;
+}
+
+int countpairs_xi(const cp_points *d, const double *edges, int nedges, const cp_options *o,
+                  uint64_t *npairs, double *wsum, double *ravg) {
+  try {
+    Call c{XI, false, d, nullptr, edges, nedges, 0.0, 1, o};
+    return run(c, npairs, wsum, ravg);
+  } catch (...) {
+    return fail(CP_ERR_INTERNAL, "unexpected exception");
+  }
+}
+
+int countpairs_wp(const cp_points *d, const double *rp_edges, int nedges, double pimax,
+                  int npibins, const cp_options *o, uint64_t *npairs, double *wsum,
+                  double *rpavg) {
+  try {
+    Call c{WP, false, d, nullptr, rp_edges, nedges, pimax, npibins, o};
+    return run(c, npairs, wsum, rpavg);
+  } catch (...) {
+    return fail(CP_ERR_INTERNAL, "unexpected exception");
+  }
+}
+
+int countpairs_cross(const cp_points *d1, const cp_points *d2, const double *edges, int nedges,
+                     const cp_options *o, uint64_t *npairs, double *wsum, double *ravg) {
+  try {
+    Call c{XI, true, d1, d2, edges, nedges, 0.0, 1, o};
+    return run(c, npairs, wsum, ravg);
+  } catch (...) {
+    return fail(CP_ERR_INTERNAL, "unexpected exception");
+  }
+}
+
+int countpairs_cross_wp(const cp_points *d1, const cp_points *d2, const double *rp_edges,
+                        int nedges, double pimax, int npibins, const cp_options *o,
+                        uint64_t *npairs, double *wsum, double *rpavg) {
+  try {
+    Call c{WP, true, d1, d2, rp_edges, nedges, pimax, npibins, o};
+    return run(c, npairs, wsum, rpavg);
+  } catch (...) {
+    return fail(CP_ERR_INTERNAL, "unexpected exception");
+  }
+}
+
+const char *countpairs_strerror(int code) {
+  switch (code) {
+  case CP_OK: return "ok";
+  case CP_ERR_INVALID_ARG: return "invalid argument";
+  case CP_ERR_OUT_OF_BOX: return "coordinate outside the periodic box";
+  case CP_ERR_NONFINITE: return "non-finite coordinate or weight";
+  case CP_ERR_NOMEM: return "out of device memory or workspace too small";
+  case CP_ERR_DEVICE: return "HIP runtime error";
+  case CP_ERR_INTERNAL: return "internal consistency check failed";
+  default: return "unknown error";
+  }
+}
+
+const char *countpairs_last_error(void) { return g_err.c_str(); }
+
+int countpairs_last_stats(cp_stats *out) {
+  if (!out) return CP_ERR_INVALID_ARG;
+  if (!g_stats_valid) return fail(CP_ERR_INVALID_ARG, "no successful call on this thread");
+  *out = g_stats;
+  return CP_OK;
+}
+
+} // extern "C"
+
+extern "C" size_t countpairs_workspace_size(int kind, int64_t n1, int64_t n2, const double *edges,
+                                            int nedges, double pimax, int npibins,
+                                            const cp_options *o) {
+  (void)edges;
+  (void)pimax;
+  (void)o;
+  if (n1 < 0 || n2 < 0 || nedges < 2) return 0;
+  const bool cross = kind >= 2;
+  const int npi = (kind == 1 || kind == 3) ? std::max(1, npibins) : 1;
+  const int64_t ntot = n1 + (cross ? n2 : 0);
+  const int64_t ncell = std::max<int64_t>(4096, 4 * ntot);   // the cell-count cap
+  const int64_t ncol = std::min<int64_t>(ncell, (int64_t)kMaxAxisCells * kMaxAxisCells);
+  Carver cv(nullptr, true);
+  SetBufs S1, S2;
+  carve_set(cv, S1, n1, ncell, ncol, true, max_tiles_bound(n1, ncell, ncol));
+  if (cross) carve_set(cv, S2, n2, ncell, ncol, false, 0);
+  const int nout = (nedges - 1) * npi;
+  cv.take<Smalls>(1);
+  cv.take<uint2>(4096);
+  cv.take<uint2>(4096);
+  cv.take<double>(nedges);
+  cv.take<unsigned long long>(nout);
+  cv.take<double>(nout);
+  cv.take<double>(nout);
+  cv.take<unsigned long long>(5);
+  cv.take<int>(1);
+  return cv.off + 256;
+}
+
+// ================================================================== plans
+
+namespace cp {
+
+struct Batch {
+  bool on = false;
+  int mode = XI, prec = F32R;
+  Geometry g;
+  Binning B;
+  int nb = 0, npi = 1, nout = 0;
+  int64_t ncell = 0, ncol = 0, ncell_tot = 0, ncol_tot = 0, npts_tot = 0, maxtiles = 0;
+  std::vector<GridGeom> geoms;
+  std::vector<ScanSeg> segs;      // nmock cell segments, then 1 column segment
+  std::vector<int64_t> cell_prefix, col_prefix;
+  std::vector<int> maxspan;
+  // device
+  GridGeom *d_geom = nullptr;
+  PointsDev *d_pts = nullptr;
+  ScanSeg *d_segs = nullptr;
+  int64_t *d_cell_prefix = nullptr, *d_col_prefix = nullptr;
+  int *d_maxspan = nullptr;
+  SetBufs S{};
+  uint2 *d_t32 = nullptr, *d_t64 = nullptr;
+  double *d_E = nullptr;
+  unsigned long long *d_hist = nullptr, *d_stats = nullptr;
+  double *d_hw = nullptr, *d_hwr = nullptr;
+  int *d_err = nullptr;
+  size_t lds = 0;
+  int nwaves = 4;
+  PairParams P{};
+};
+
+} // namespace cp
+
+struct cp_plan {
+  int nmock = 0;
+  std::vector<int> order;        // queue position -> caller's index
+  std::vector<int64_t> n;        // points per catalogue (queue order)
+  int64_t maxn = 0;
+  std::vector<cp::PointsDev> pts;
+  cp::Batch xi, wp;
+  int count_mode = CP_ORDERED;
+  void *mem = nullptr;
+  hipStream_t cap = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  bool use_graph = true;
+  hipEvent_t ev[5] = {};
+};
+
+namespace cp {
+
+static int batch_prepare(cp_plan &pl, Batch &b, int mode, int prec, const double *edges,
+                         int nedges, double pimax, int npi, const cp_options &o) {
+  b.on = true;
+  b.mode = mode;
+  b.nb = nedges - 1;
+  b.npi = mode == WP ? npi : 1;
+  b.nout = b.nb * b.npi;
+  const double lo[3] = {0, 0, 0}, ext[3] = {0, 0, 0};
+  b.g = choose_geometry(mode, true, o.boxsize, lo, ext, edges[nedges - 1], pimax, o.refine,
+                        pl.maxn);
+  b.prec = (b.g.wrap[0] || b.g.wrap[1] || b.g.wrap[2]) ? F64 : prec;
+  int rc = make_binning(mode, b.prec, edges, nedges, pimax, b.npi, b.g, o.boxsize, b.B);
+  if (rc) return rc;
+  b.ncell = (int64_t)b.g.n[0] * b.g.n[1] * b.g.n[2];
+  b.ncol = (int64_t)b.g.n[0] * b.g.n[1];
+  b.geoms.clear();
+  b.segs.clear();
+  b.cell_prefix.assign(1, 0);
+  b.col_prefix.assign(1, 0);
+  b.maxspan.clear();
+  int64_t pb = 0;
+  for (int m = 0; m < pl.nmock; m++) {
+    const int64_t cbase = b.ncell * m, sbase = (b.ncell + 1) * m, colbase = b.ncol * m;
+    b.geoms.push_back(to_dev_geom(b.g, true, o.boxsize, pb, cbase, sbase, pl.n[m], colbase));
+    b.segs.push_back({cbase, sbase, b.ncell});
+    b.cell_prefix.push_back(b.ncell * (m + 1));
+    b.col_prefix.push_back(b.ncol * (m + 1));
+    b.maxspan.push_back(b.g.maxspan);
+    pb += pl.n[m];
+  }
+  b.npts_tot = pb;
+  b.ncell_tot = b.ncell * pl.nmock;
+  b.ncol_tot = b.ncol * pl.nmock;
+  b.segs.push_back({0, 0, b.ncol_tot});
+  b.maxtiles = max_tiles_bound(b.npts_tot, b.ncell_tot, b.ncol_tot);
+  b.nwaves = 4;
+  const LdsLayout LY = lds_layout_host(mode, b.prec, 0, (int)b.B.t32.e.size(),
+                                       (int)b.B.t64.e.size(), b.nb, b.npi);
+  b.lds = LY.common + b.nwaves * LY.wave_bytes;
+  if (b.lds > 160 * 1024) return fail(CP_ERR_INVALID_ARG, "too many bins for the LDS budget");
+  return CP_OK;
+}
+
+static void batch_carve(Carver &cv, cp_plan &pl, Batch &b) {
+  if (!b.on) return;
+  const int nm = pl.nmock;
+  b.d_geom = cv.take<GridGeom>(nm);
+  b.d_pts = cv.take<PointsDev>(nm);
+  b.d_segs = cv.take<ScanSeg>(nm + 1);
+  b.d_cell_prefix = cv.take<int64_t>(nm + 1);
+  b.d_col_prefix = cv.take<int64_t>(nm + 1);
+  b.d_maxspan = cv.take<int>(nm);
+  // cell_start needs ncell + 1 per catalogue
+  b.S.ccount = cv.take<int>(b.ncell_tot);
+  b.S.cstart = cv.take<int>(b.ncell_tot + nm);
+  b.S.cid = cv.take<int>(std::max<int64_t>(b.npts_tot, 1));
+  b.S.rank = cv.take<int>(std::max<int64_t>(b.npts_tot, 1));
+  b.S.pos = cv.take<double4>(std::max<int64_t>(b.npts_tot, 1));
+  b.S.strm = cv.take<float4>(std::max<int64_t>(b.npts_tot, 1));
+  b.S.cbox = cv.take<CellBox>(b.ncell_tot);
+  b.S.colcnt = cv.take<int>(b.ncol_tot + 1);
+  b.S.coloff = cv.take<int>(b.ncol_tot + 1);
+  b.S.tiles = cv.take<Tile>(b.maxtiles);
+  b.d_t32 = cv.take<uint2>(b.B.t32.e.size());
+  b.d_t64 = cv.take<uint2>(b.B.t64.e.size());
+  b.d_E = cv.take<double>(b.nb + 1);
+  b.d_hist = cv.take<unsigned long long>((int64_t)b.nout * nm);
+  b.d_hw = cv.take<double>(1);
+  b.d_hwr = cv.take<double>(1);
+  b.d_stats = cv.take<unsigned long long>(5);
+  b.d_err = cv.take<int>(1);
+}
+
+static int batch_upload(cp_plan &pl, Batch &b) {
+  if (!b.on) return CP_OK;
+  const int nm = pl.nmock;
+  HIPCHK(hipMemcpy(b.d_geom, b.geoms.data(), sizeof(GridGeom) * nm, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(b.d_pts, pl.pts.data(), sizeof(PointsDev) * nm, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(b.d_segs, b.segs.data(), sizeof(ScanSeg) * (nm + 1), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(b.d_cell_prefix, b.cell_prefix.data(), 8 * (nm + 1), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(b.d_col_prefix, b.col_prefix.data(), 8 * (nm + 1), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(b.d_maxspan, b.maxspan.data(), 4 * nm, hipMemcpyHostToDevice));
+  if (!b.B.t32.e.empty())
+    HIPCHK(hipMemcpy(b.d_t32, b.B.t32.e.data(), 8 * b.B.t32.e.size(), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(b.d_t64, b.B.t64.e.data(), 8 * b.B.t64.e.size(), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(b.d_E, b.B.E.data(), 8 * (b.nb + 1), hipMemcpyHostToDevice));
+  PairParams &P = b.P;
+  memset(&P, 0, sizeof(P));
+  P.tiles = b.S.tiles;
+  P.ntiles = b.S.coloff + b.ncol_tot;
+  P.qhead = b.d_stats + 4;
+  P.geom1 = b.d_geom;
+  P.geom2 = b.d_geom;
+  P.pos1 = b.S.pos;
+  P.pos2 = b.S.pos;
+  P.strm2 = b.S.strm;
+  P.cstart2 = b.S.cstart;
+  P.cbox2 = b.S.cbox;
+  P.tab32 = b.B.t32.e.empty() ? b.d_t64 : b.d_t32;
+  P.tab64 = b.d_t64;
+  P.tab32_lo = b.B.t32.lo;
+  P.tab32_hi = b.B.t32.hi;
+  P.tab64_lo = b.B.t64.lo;
+  P.tab64_hi = b.B.t64.hi;
+  P.tab_shift = b.B.shift;
+  P.E = b.d_E;
+  P.nb = b.nb;
+  P.nslots = b.nb + 2;
+  P.AB32 = b.B.AB32;
+  P.EB = b.B.E[b.nb];
+  P.pimax = b.mode == WP ? std::sqrt(0.0) + b.B.dpi * b.npi : 0.0;
+  P.dpi = b.B.dpi;
+  P.npi = b.npi;
+  P.inv_dpi32 = b.B.inv_dpi32;
+  P.pi_delta = b.B.pi_delta;
+  P.pi_lo32 = b.B.pi_lo32;
+  P.pi_hi32 = b.B.pi_hi32;
+  P.autocorr = 1;
+  P.weighted = 0;
+  P.hist = b.d_hist;
+  P.hw = b.d_hw;
+  P.hwr = b.d_hwr;
+  P.stats = b.d_stats;
+  P.hist_stride = b.nout;
+  return CP_OK;
+}
+
+static int batch_enqueue(cp_plan &pl, Batch &b, hipStream_t st) {
+  if (!b.on) return CP_OK;
+  const int nm = pl.nmock;
+  auto blocks = [](int64_t n, int per, int cap) {
+    return (int)std::min<int64_t>(std::max<int64_t>((n + per - 1) / per, 1), cap);
+  };
+  hipLaunchKernelGGL(k_fill_i32, dim3(blocks(b.ncell_tot, 256, 8192)), dim3(256), 0, st,
+                     b.S.ccount, b.ncell_tot, 0);
+  hipLaunchKernelGGL(k_fill_u64, dim3(blocks((int64_t)b.nout * nm, 256, 1024)), dim3(256), 0, st,
+                     b.d_hist, (int64_t)b.nout * nm);
+  hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, b.d_stats, (int64_t)5);
+  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, b.d_err, (int64_t)1, 0);
+  hipLaunchKernelGGL(k_assign, dim3(blocks(pl.maxn, 256, 4096), nm), dim3(256), 0, st, b.d_pts,
+                     b.d_geom, b.S.ccount, b.S.cid, b.S.rank, b.d_err);
+  hipLaunchKernelGGL(k_scan_segments, dim3(nm), dim3(1024), 0, st, b.S.ccount, b.S.cstart,
+                     b.d_segs);
+  hipLaunchKernelGGL(k_scatter, dim3(blocks(pl.maxn, 256, 4096), nm), dim3(256), 0, st, b.d_pts,
+                     b.d_geom, b.S.cstart, b.S.cid, b.S.rank, b.S.pos, b.S.strm, b.mode);
+  hipLaunchKernelGGL(k_cellbox, dim3(blocks(b.ncell_tot, 4, 65536)), dim3(256), 0, st, b.d_geom,
+                     nm, b.S.cstart, b.S.pos, b.S.cbox, b.d_cell_prefix);
+  const int tb = blocks(b.ncol_tot, 256, 65536);
+  hipLaunchKernelGGL(k_tiles, dim3(tb), dim3(256), 0, st, b.d_geom, nm, b.S.cstart, b.d_maxspan,
+                     b.d_col_prefix, b.S.colcnt, b.S.coloff, b.S.tiles, 0);
+  hipLaunchKernelGGL(k_scan_segments, dim3(1), dim3(1024), 0, st, b.S.colcnt, b.S.coloff,
+                     b.d_segs + nm);
+  hipLaunchKernelGGL(k_tiles, dim3(tb), dim3(256), 0, st, b.d_geom, nm, b.S.cstart, b.d_maxspan,
+                     b.d_col_prefix, b.S.colcnt, b.S.coloff, b.S.tiles, 1);
+  return launch_pairs(st, b.mode, b.prec, 0, b.P, b.lds, b.nwaves);
+}
+
+static int plan_enqueue(cp_plan &pl, hipStream_t st) {
+  int rc;
+  HIPCHK(hipEventRecord(pl.ev[0], st));
+  if ((rc = batch_enqueue(pl, pl.xi, st))) return rc;
+  HIPCHK(hipEventRecord(pl.ev[1], st));
+  if ((rc = batch_enqueue(pl, pl.wp, st))) return rc;
+  HIPCHK(hipEventRecord(pl.ev[2], st));
+  return CP_OK;
+}
+
+} // namespace cp
+
+extern "C" {
+
+int cp_plan_destroy(cp_plan *pl) {
+  if (!pl) return CP_OK;
+  if (pl->gexec) (void)hipGraphExecDestroy(pl->gexec);
+  if (pl->cap) (void)hipStreamDestroy(pl->cap);
+  for (auto &e : pl->ev)
+    if (e) (void)hipEventDestroy(e);
+  if (pl->mem) (void)hipFree(pl->mem);
+  delete pl;
+  return CP_OK;
+}
+
+int cp_plan_create(const cp_points *mocks, int nmocks, const double *xi_edges, int xi_nedges,
+                   const double *wp_edges, int wp_nedges, double pimax, int npibins,
+                   const cp_options *o, cp_plan **out) {
+  try {
+    if (!out) return fail(CP_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!mocks || nmocks < 1 || nmocks > 65535)
+      return fail(CP_ERR_INVALID_ARG, "need 1..65535 catalogues");
+    if (!o) return fail(CP_ERR_INVALID_ARG, "options is NULL");
+    if (!o->periodic) return fail(CP_ERR_INVALID_ARG, "plans need a periodic box");
+    if (!xi_edges && !wp_edges) return fail(CP_ERR_INVALID_ARG, "no statistic requested");
+    int rc;
+    for (int m = 0; m < nmocks; m++) {
+      std::string nm = "mocks[" + std::to_string(m) + "]";
+      if ((rc = check_points(&mocks[m], nm.c_str()))) return rc;
+    }
+    if (xi_edges) {
+      Call c{XI, false, &mocks[0], nullptr, xi_edges, xi_nedges, 0.0, 1, o};
+      if ((rc = check_common(c))) return rc;
+    }
+    if (wp_edges) {
+      Call c{WP, false, &mocks[0], nullptr, wp_edges, wp_nedges, pimax, npibins, o};
+      if ((rc = check_common(c))) return rc;
+    }
+    cp_plan *pl = new cp_plan();
+    pl->nmock = nmocks;
+    pl->count_mode = o->count_mode;
+    pl->order.resize(nmocks);
+    for (int m = 0; m < nmocks; m++) pl->order[m] = m;
+    // longest first: the queue hands out the biggest catalogues' tiles first
+    std::stable_sort(pl->order.begin(), pl->order.end(),
+                     [&](int a, int b) { return mocks[a].n > mocks[b].n; });
+    for (int q = 0; q < nmocks; q++) {
+      const cp_points &p = mocks[pl->order[q]];
+      pl->n.push_back(p.n);
+      pl->maxn = std::max(pl->maxn, p.n);
+      PointsDev d;
+      d.x = p.x;
+      d.y = p.y;
+      d.z = p.z;
+      d.w = nullptr;   // plans count pairs only
+      d.n = p.n;
+      d.dtype = p.dtype;
+      d.pad = 0;
+      pl->pts.push_back(d);
+    }
+    const int prec = o->precision == CP_PREC_FP32_RECHECK ? F32R : F64;
+    if (xi_edges && (rc = batch_prepare(*pl, pl->xi, XI, prec, xi_edges, xi_nedges, 0.0, 1, *o))) {
+      cp_plan_destroy(pl);
+      return rc;
+    }
+    if (wp_edges &&
+        (rc = batch_prepare(*pl, pl->wp, WP, prec, wp_edges, wp_nedges, pimax, npibins, *o))) {
+      cp_plan_destroy(pl);
+      return rc;
+    }
+    Carver dry(nullptr, true);
+    batch_carve(dry, *pl, pl->xi);
+    batch_carve(dry, *pl, pl->wp);
+    if (hipMalloc(&pl->mem, dry.off + 256) != hipSuccess) {
+      pl->mem = nullptr;
+      cp_plan_destroy(pl);
+      return fail(CP_ERR_NOMEM, "plan allocation of " + std::to_string(dry.off) + " bytes failed");
+    }
+    Carver cv(pl->mem, false);
+    batch_carve(cv, *pl, pl->xi);
+    batch_carve(cv, *pl, pl->wp);
+    if ((rc = batch_upload(*pl, pl->xi)) || (rc = batch_upload(*pl, pl->wp))) {
+      cp_plan_destroy(pl);
+      return rc;
+    }
+    if (wp_edges) pl->wp.P.pimax = pimax;
+    for (auto &e : pl->ev) {
+      if (hipEventCreate(&e) != hipSuccess) {
+        cp_plan_destroy(pl);
+        return fail(CP_ERR_DEVICE, "hipEventCreate failed");
+      }
+    }
+    if (hipStreamCreateWithFlags(&pl->cap, hipStreamNonBlocking) != hipSuccess) {
+      cp_plan_destroy(pl);
+      return fail(CP_ERR_DEVICE, "hipStreamCreate failed");
+    }
+    const char *env = getenv("CP_PLAN_NO_GRAPH");
+    pl->use_graph = !(env && env[0] == '1');
+    *out = pl;
+    return CP_OK;
+  } catch (...) {
+    return fail(CP_ERR_INTERNAL, "unexpected exception");
+  }
+}
+
+int cp_plan_execute(cp_plan *pl, void *stream) {
+  if (!pl) return fail(CP_ERR_INVALID_ARG, "plan is NULL");
+  hipStream_t st = (hipStream_t)stream;
+  if (!pl->use_graph) return plan_enqueue(*pl, st);
+  if (!pl->gexec) {
+    // capture the whole pipeline once on the plan's own stream
+    HIPCHK(hipStreamBeginCapture(pl->cap, hipStreamCaptureModeThreadLocal));
+    int rc = plan_enqueue(*pl, pl->cap);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(pl->cap, &graph);
+    if (rc) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return rc;
+    }
+    if (e != hipSuccess) return fail(CP_ERR_DEVICE, "graph capture failed");
+    e = hipGraphInstantiate(&pl->gexec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+      pl->gexec = nullptr;
+      return fail(CP_ERR_DEVICE, "graph instantiation failed");
+    }
+  }
+  HIPCHK(hipGraphLaunch(pl->gexec, st));
+  return CP_OK;
+}
+
+int cp_plan_results(cp_plan *pl, uint64_t *xi_npairs, uint64_t *wp_npairs) {
+  if (!pl) return fail(CP_ERR_INVALID_ARG, "plan is NULL");
+  HIPCHK(hipDeviceSynchronize());
+  int flags = 0;
+  const double mult = pl->count_mode == CP_ORDERED ? 2 : 1;
+  for (int s = 0; s < 2; s++) {
+    Batch &b = s ? pl->wp : pl->xi;
+    uint64_t *out = s ? wp_npairs : xi_npairs;
+    if (!b.on) continue;
+    int f = 0;
+    HIPCHK(hipMemcpy(&f, b.d_err, sizeof(int), hipMemcpyDeviceToHost));
+    flags |= f;
+    if (!out) continue;
+    std::vector<unsigned long long> h((size_t)b.nout * pl->nmock);
+    HIPCHK(hipMemcpy(h.data(), b.d_hist, 8 * h.size(), hipMemcpyDeviceToHost));
+    for (int q = 0; q < pl->nmock; q++) {
+      const int m = pl->order[q];
+      for (int k = 0; k < b.nout; k++)
+        out[(size_t)m * b.nout + k] = (uint64_t)h[(size_t)q * b.nout + k] * (uint64_t)mult;
+    }
+  }
+  return map_err_flags(flags);
+}
+
+int cp_plan_stats(cp_plan *pl, cp_stats *xs, cp_stats *ws) {
+  if (!pl) return fail(CP_ERR_INVALID_ARG, "plan is NULL");
+  HIPCHK(hipDeviceSynchronize());
+  for (int s = 0; s < 2; s++) {
+    Batch &b = s ? pl->wp : pl->xi;
+    cp_stats *o = s ? ws : xs;
+    if (!o) continue;
+    memset(o, 0, sizeof(*o));
+    if (!b.on) continue;
+    unsigned long long st[5];
+    int nt = 0;
+    HIPCHK(hipMemcpy(st, b.d_stats, sizeof(st), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(&nt, b.S.coloff + b.ncol_tot, sizeof(int), hipMemcpyDeviceToHost));
+    o->candidates = st[0];
+    o->rechecks = st[1];
+    o->cell_pairs = st[2];
+    o->cell_pairs_pruned = st[3];
+    o->tiles = nt;
+    for (int a = 0; a < 3; a++) {
+      o->grid[a] = b.g.n[a];
+      o->refine[a] = b.g.r[a];
+    }
+    float ms = 0;
+    if (hipEventElapsedTime(&ms, pl->ev[s], pl->ev[s + 1]) == hipSuccess) o->ms_pairs = ms;
+    if (hipEventElapsedTime(&ms, pl->ev[0], pl->ev[2]) == hipSuccess) o->ms_total = ms;
+  }
+  return CP_OK;
+}
+
+} // extern "C"

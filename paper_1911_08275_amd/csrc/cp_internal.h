@@ -1,0 +1,123 @@
+// Internal types shared by the host side and the kernels of libcountpairs.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cp {
+
+constexpr int kWave = 64;
+constexpr int kTileMax = 64;        // points per primary tile (one per lane)
+constexpr int kMaxAxisCells = 1023; // cells per axis (packed in 10 bits)
+constexpr int kMaxBins = 60;        // separation bins; slots 0 and nb+1 are trash and
+                                    // slot + 1 must fit the 6-bit table code
+constexpr int kMaxPiBins = 256;
+
+enum Mode { XI = 0, WP = 1 };
+enum Prec { F64 = 0, F32R = 1 };
+
+// Geometry of one catalogue's cell grid.  Cells are ordered x-major, z
+// fastest: cell = (cx * ny + cy) * nz + cz, so a run of z-cells in one
+// (x, y) column is contiguous in the sorted point arrays.
+struct GridGeom {
+  int n[3];        // cells per axis
+  int r[3];        // neighbour reach in cells per axis
+  int wrap[3];     // 1: single periodic cell on this axis, per-pair minimum image
+  int periodic;
+  double lo[3];    // domain origin
+  double cs[3];    // cell side
+  double inv[3];   // 1 / cell side
+  double box;      // periodic side
+  double halfbox;
+  int64_t pbase;   // first sorted point of this catalogue
+  int64_t cbase;   // first entry of this catalogue in cell arrays
+  int64_t sbase;   // first entry of this catalogue in cell_start (ncell + 1 per catalogue)
+  int64_t npts;
+  int ncell;
+  int ncol;
+  int64_t colbase; // first entry of this catalogue in per-column arrays
+};
+
+// Input point set on the device (one catalogue).
+struct PointsDev {
+  const void *x, *y, *z;
+  const double *w;
+  int64_t n;
+  int dtype;       // 0 f64, 1 f32
+  int pad;
+};
+
+struct CellBox {
+  double lo[3];
+  double hi[3];
+};
+
+// A primary tile: <= 64 consecutive sorted points of one column whose cells
+// span z-cells [cz0, cz1].
+struct Tile {
+  int64_t p0;      // first sorted point (absolute)
+  int n;           // points in the tile
+  int mock;        // catalogue index
+  int col;         // column cx * ny + cy
+  int cz0, cz1;
+  int pad;
+};
+
+struct PairParams {
+  // work queue
+  const Tile *tiles;
+  const int *ntiles;         // device: number of tiles in the queue
+  unsigned long long *qhead;
+  // geometry (indexed by tile.mock); set 2 is the searched (streamed) set
+  const GridGeom *geom1;
+  const GridGeom *geom2;
+  const double4 *pos1;       // sorted (x, y, z, w) of set 1 (tiles)
+  const double4 *pos2;       // sorted (x, y, z, w) of set 2
+  const float4 *strm2;       // sorted cell-local binary32 stream of set 2
+  const int *cstart2;        // cell starts of set 2 (relative to pbase)
+  const CellBox *cbox2;      // cell bounding boxes of set 2
+  // binning
+  const uint2 *tab32;        // binary32 decision table (FP32 mode)
+  const uint2 *tab64;        // decision table for fl32(s64) (FP64 values)
+  int tab32_lo, tab32_hi, tab64_lo, tab64_hi;
+  int tab_shift;
+  const double *E;           // squared edges, nb + 1
+  int nb;                    // separation bins
+  int nslots;                // nb + 2
+  float AB32;                // binary32 s~ >= AB32 -> certainly >= E_B
+  double EB;                 // E_B
+  // wp
+  double pimax, dpi;
+  int npi;
+  float inv_dpi32, pi_delta, pi_lo32, pi_hi32;
+  // flags
+  int autocorr;
+  int weighted;
+  // outputs (per catalogue)
+  unsigned long long *hist;  // [nmock][nb * npi]
+  double *hw;                // [nmock][nb * npi] sum of weights
+  double *hwr;               // [nmock][nb * npi] sum of weight * separation
+  unsigned long long *stats; // candidates, rechecks, cellpairs, pruned
+  int hist_stride;           // nb * npi
+};
+
+} // namespace cp
+
+namespace cp {
+
+// Frame origin of a cell along axis a: the cell centre in binary64.  The
+// cell build and the pair kernels must evaluate this identically (same
+// expression, no contraction) so binary32 offsets from it are consistent.
+__host__ __device__ inline double frame_origin(const GridGeom &g, int a, int c) {
+  double t = ((double)c + 0.5) * g.cs[a];
+  return g.lo[a] + t;
+}
+
+__host__ __device__ inline int cell_coord(const GridGeom &g, int a, double v) {
+  double t = (v - g.lo[a]) * g.inv[a];
+  if (!(t >= 0.0)) return 0;              // also NaN (rejected elsewhere)
+  if (t >= (double)g.n[a]) return g.n[a] - 1;
+  return (int)t;                          // t >= 0: truncation is floor
+}
+
+} // namespace cp

@@ -1,0 +1,321 @@
+// Cell-list build on the device: bounding box, cell assignment, counting
+// sort into cell-ordered SoA, per-cell bounding boxes and primary tiles.
+//
+// Section 2.1 ("Creating 3D cells", "Improving cache utilization"): the
+// library computes the bounding box of the data, divides it into cells whose
+// side is a fraction of R_max (of pi_max along z for wp) and copies each
+// cell's points into contiguous per-cell storage.  Section 2.2: each cell
+// also keeps the bounding box of its members for the minimum-separation test.
+#include "cp_internal.h"
+
+#include <float.h>
+
+namespace cp {
+
+// Error bits raised by the cell build; the host maps them to status codes.
+enum { ERRF_NONFINITE = 1, ERRF_OUT_OF_BOX = 2 };
+
+__device__ inline double load_coord(const void *p, int dtype, int64_t i) {
+  return dtype == 0 ? ((const double *)p)[i] : (double)((const float *)p)[i];
+}
+
+// ------------------------------------------------------------ bounding box
+
+// Partial min/max of up to two point sets; out[blk * 6 + {0..5}] =
+// (min x, min y, min z, max x, max y, max z).  Non-finite values set
+// ERRF_NONFINITE and are left out.
+__global__ __launch_bounds__(256) void k_bbox_partial(PointsDev a, PointsDev b,
+                                                      double *out, int *err) {
+  double mn[3] = {DBL_MAX, DBL_MAX, DBL_MAX};
+  double mx[3] = {-DBL_MAX, -DBL_MAX, -DBL_MAX};
+  int bad = 0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int s = 0; s < 2; s++) {
+    const PointsDev &P = s ? b : a;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < P.n; i += stride) {
+      double v[3] = {load_coord(P.x, P.dtype, i), load_coord(P.y, P.dtype, i),
+                     load_coord(P.z, P.dtype, i)};
+      bool fin = isfinite(v[0]) && isfinite(v[1]) && isfinite(v[2]);
+      if (P.w) fin = fin && isfinite(P.w[i]);
+      if (!fin) {
+        bad = 1;
+        continue;
+      }
+      for (int k = 0; k < 3; k++) {
+        mn[k] = fmin(mn[k], v[k]);
+        mx[k] = fmax(mx[k], v[k]);
+      }
+    }
+  }
+  if (bad) atomicOr(err, ERRF_NONFINITE);
+  __shared__ double red[6][256];
+  for (int k = 0; k < 3; k++) {
+    red[k][threadIdx.x] = mn[k];
+    red[k + 3][threadIdx.x] = mx[k];
+  }
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      for (int k = 0; k < 3; k++) {
+        red[k][threadIdx.x] = fmin(red[k][threadIdx.x], red[k][threadIdx.x + w]);
+        red[k + 3][threadIdx.x] = fmax(red[k + 3][threadIdx.x], red[k + 3][threadIdx.x + w]);
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < 6) out[blockIdx.x * 6 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ __launch_bounds__(64) void k_bbox_final(const double *part, int nblk, double *out) {
+  int k = threadIdx.x;
+  if (k >= 6) return;
+  double v = k < 3 ? DBL_MAX : -DBL_MAX;
+  for (int b = 0; b < nblk; b++) v = k < 3 ? fmin(v, part[b * 6 + k]) : fmax(v, part[b * 6 + k]);
+  out[k] = v;
+}
+
+// --------------------------------------------------------- fills and scans
+
+__global__ void k_fill_i32(int *p, int64_t n, int v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+__global__ void k_fill_u64(unsigned long long *p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0ull;
+}
+
+__global__ void k_fill_f64(double *p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0.0;
+}
+
+struct ScanSeg {
+  int64_t in_off;
+  int64_t out_off;
+  int64_t len;
+};
+
+// Exclusive scan of one segment per block: out[0..len] with out[len] = total.
+// Each of the 1024 threads sums a contiguous chunk, the block scans the
+// chunk sums, then each thread writes its chunk.
+__global__ __launch_bounds__(1024) void k_scan_segments(const int *in, int *out,
+                                                        const ScanSeg *segs) {
+  const ScanSeg S = segs[blockIdx.x];
+  const int *src = in + S.in_off;
+  int *dst = out + S.out_off;
+  const int64_t per = (S.len + blockDim.x - 1) / blockDim.x;
+  const int64_t b = per * threadIdx.x;
+  const int64_t e = b + per < S.len ? b + per : S.len;
+  int sum = 0;
+  for (int64_t i = b; i < e; i++) sum += src[i];
+  __shared__ int sh[1024];
+  sh[threadIdx.x] = sum;
+  __syncthreads();
+  for (int off = 1; off < (int)blockDim.x; off <<= 1) {
+    int v = (int)threadIdx.x >= off ? sh[threadIdx.x - off] : 0;
+    __syncthreads();
+    sh[threadIdx.x] += v;
+    __syncthreads();
+  }
+  int run = sh[threadIdx.x] - sum;
+  for (int64_t i = b; i < e; i++) {
+    int v = src[i];
+    dst[i] = run;
+    run += v;
+  }
+  if (threadIdx.x == blockDim.x - 1) dst[S.len] = sh[threadIdx.x];
+}
+
+// --------------------------------------------------------- cell assignment
+
+// One catalogue per blockIdx.y.  Validates the points (finite; inside
+// [0, box) when periodic), computes their cell and takes a rank inside the
+// cell with an atomic counter (the order inside a cell is arbitrary; counts
+// do not depend on it).
+__global__ __launch_bounds__(256) void k_assign(const PointsDev *pts, const GridGeom *geom,
+                                                int *cell_count, int *cid, int *rank,
+                                                int *err) {
+  const PointsDev P = pts[blockIdx.y];
+  const GridGeom &G = geom[blockIdx.y];
+  int bad = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < P.n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    double v[3] = {load_coord(P.x, P.dtype, i), load_coord(P.y, P.dtype, i),
+                   load_coord(P.z, P.dtype, i)};
+    int c[3];
+    for (int a = 0; a < 3; a++) {
+      if (!isfinite(v[a])) bad |= ERRF_NONFINITE;
+      else if (G.periodic && (v[a] < 0.0 || v[a] >= G.box)) bad |= ERRF_OUT_OF_BOX;
+      c[a] = cell_coord(G, a, v[a]);
+    }
+    if (P.w && !isfinite(P.w[i])) bad |= ERRF_NONFINITE;
+    int cell = (c[0] * G.n[1] + c[1]) * G.n[2] + c[2];
+    cid[G.pbase + i] = cell;
+    rank[G.pbase + i] = atomicAdd(&cell_count[G.cbase + cell], 1);
+  }
+  if (bad) atomicOr(err, bad);
+}
+
+// Scatter into cell order: binary64 (x, y, z, w) and the binary32 stream
+// record used by the pair kernels, in the frame of the point's own cell:
+//   xi: (-2 px, -2 py, -2 pz, |p|^2)      wp: (-2 px, -2 py, pz, px^2 + py^2)
+// with p = fl32(x - O_cell) and O_cell the cell centre.
+__global__ __launch_bounds__(256) void k_scatter(const PointsDev *pts, const GridGeom *geom,
+                                                 const int *cstart, const int *cid,
+                                                 const int *rank, double4 *pos,
+                                                 float4 *strm, int mode) {
+  const PointsDev P = pts[blockIdx.y];
+  const GridGeom &G = geom[blockIdx.y];
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < P.n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int cell = cid[G.pbase + i];
+    const int64_t dst = G.pbase + cstart[G.sbase + cell] + rank[G.pbase + i];
+    double v[3] = {load_coord(P.x, P.dtype, i), load_coord(P.y, P.dtype, i),
+                   load_coord(P.z, P.dtype, i)};
+    double w = P.w ? P.w[i] : 1.0;
+    pos[dst] = make_double4(v[0], v[1], v[2], w);
+    int cz = cell % G.n[2];
+    int cy = (cell / G.n[2]) % G.n[1];
+    int cx = cell / (G.n[2] * G.n[1]);
+    float px = (float)(v[0] - frame_origin(G, 0, cx));
+    float py = (float)(v[1] - frame_origin(G, 1, cy));
+    float pz = (float)(v[2] - frame_origin(G, 2, cz));
+    float4 s;
+    s.x = -2.0f * px;
+    s.y = -2.0f * py;
+    if (mode == XI) {
+      s.z = -2.0f * pz;
+      s.w = __builtin_fmaf(pz, pz, __builtin_fmaf(py, py, px * px));
+    } else {
+      s.z = pz;
+      s.w = __builtin_fmaf(py, py, px * px);
+    }
+    strm[dst] = s;
+  }
+}
+
+// Per-cell bounding boxes (binary64), one wave per cell.
+__global__ __launch_bounds__(256) void k_cellbox(const GridGeom *geom, int nmock,
+                                                 const int *cstart, const double4 *pos,
+                                                 CellBox *cbox, const int64_t *cell_prefix) {
+  const int wid = (int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6);
+  const int lane = threadIdx.x & 63;
+  const int64_t total = cell_prefix[nmock];
+  for (int64_t gc = wid; gc < total; gc += (int64_t)gridDim.x * (blockDim.x >> 6)) {
+    // find the catalogue of global cell gc (few catalogues per call, or a
+    // monotone prefix array for batches)
+    int lo = 0, hi = nmock - 1;
+    while (lo < hi) {
+      int mid = (lo + hi + 1) >> 1;
+      if (cell_prefix[mid] <= gc) lo = mid; else hi = mid - 1;
+    }
+    const GridGeom &G = geom[lo];
+    const int c = (int)(gc - cell_prefix[lo]);
+    const int b = cstart[G.sbase + c], e = cstart[G.sbase + c + 1];
+    double mn[3] = {DBL_MAX, DBL_MAX, DBL_MAX}, mx[3] = {-DBL_MAX, -DBL_MAX, -DBL_MAX};
+    for (int k = b + lane; k < e; k += 64) {
+      double4 p = pos[G.pbase + k];
+      mn[0] = fmin(mn[0], p.x); mx[0] = fmax(mx[0], p.x);
+      mn[1] = fmin(mn[1], p.y); mx[1] = fmax(mx[1], p.y);
+      mn[2] = fmin(mn[2], p.z); mx[2] = fmax(mx[2], p.z);
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      for (int a = 0; a < 3; a++) {
+        mn[a] = fmin(mn[a], __shfl_xor(mn[a], off));
+        mx[a] = fmax(mx[a], __shfl_xor(mx[a], off));
+      }
+    }
+    if (lane == 0) {
+      CellBox B;
+      for (int a = 0; a < 3; a++) {
+        B.lo[a] = mn[a];
+        B.hi[a] = mx[a];
+      }
+      cbox[G.cbase + c] = B;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ tiles
+
+// Greedy packing of each column's z-run of cells into tiles of <= 64
+// points and <= maxspan cells; a cell with more than 64 points is split into
+// chunks of 64.  emit = 0: count tiles per column; emit = 1: write them at
+// the offsets of the scanned counts.
+__device__ inline void walk_column(const GridGeom &G, const int *cstart, int col, int maxspan,
+                                   int mock, int emit, Tile *out, int64_t &ntile) {
+  const int nz = G.n[2];
+  int cur_n = 0, cz0 = -1;
+  int64_t cur_p0 = 0;
+  auto close = [&](int cz1) {
+    if (cz0 >= 0 && cur_n > 0) {
+      if (emit) {
+        Tile T;
+        T.p0 = G.pbase + cur_p0;
+        T.n = cur_n;
+        T.mock = mock;
+        T.col = col;
+        T.cz0 = cz0;
+        T.cz1 = cz1;
+        T.pad = 0;
+        out[ntile] = T;
+      }
+      ntile++;
+    }
+    cur_n = 0;
+    cz0 = -1;
+  };
+  int last = -1;
+  for (int z = 0; z < nz; z++) {
+    const int c = col * nz + z;
+    const int b = cstart[G.sbase + c], e = cstart[G.sbase + c + 1];
+    const int n = e - b;
+    if (n == 0) continue;
+    if (n > kTileMax) {
+      close(last);
+      for (int q = b; q < e; q += kTileMax) {
+        cz0 = z;
+        cur_p0 = q;
+        cur_n = (e - q) < kTileMax ? (e - q) : kTileMax;
+        close(z);
+      }
+      last = z;
+      continue;
+    }
+    if (cz0 >= 0 && (cur_n + n > kTileMax || z - cz0 + 1 > maxspan)) close(last);
+    if (cz0 < 0) {
+      cz0 = z;
+      cur_p0 = b;
+    }
+    cur_n += n;
+    last = z;
+  }
+  close(last);
+}
+
+__global__ __launch_bounds__(256) void k_tiles(const GridGeom *geom, int nmock,
+                                               const int *cstart, const int *maxspan,
+                                               const int64_t *col_prefix, int *colcnt,
+                                               const int *coloff, Tile *tiles, int emit) {
+  const int64_t total = col_prefix[nmock];
+  for (int64_t gcol = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gcol < total;
+       gcol += (int64_t)gridDim.x * blockDim.x) {
+    int lo = 0, hi = nmock - 1;
+    while (lo < hi) {
+      int mid = (lo + hi + 1) >> 1;
+      if (col_prefix[mid] <= gcol) lo = mid; else hi = mid - 1;
+    }
+    const GridGeom &G = geom[lo];
+    const int col = (int)(gcol - col_prefix[lo]);
+    int64_t n = emit ? coloff[gcol] : 0;
+    walk_column(G, cstart, col, maxspan[lo], lo, emit, tiles, n);
+    if (!emit) colcnt[gcol] = (int)n;
+  }
+}
+
+} // namespace cp
