@@ -1,0 +1,274 @@
+#!/usr/bin/env python3
+"""Benchmark of the MI355X pair-counting path.
+
+Default workload (the headline): xi(r) auto-count of 10^6 Neyman-Scott points
+(2*10^4 parents, mean 50 children, sigma 1.5) in a periodic cube of side 420,
+14 log bins over [0.1, 25], weights U(0.5, 1.5) with the weighted mean
+separation per bin, binary32 distances with binary64 edge recheck.  A step is
+one countpairs_xi call: cell build, pruned cell-pair walk, pair kernel and
+reduction, with the inputs already resident in HBM.
+
+Also reported (one JSON line on stdout, progress on stderr): the same step in
+plain binary64, the wp(rp) 2-D histogram on the same generator, the float32
+non-periodic cross count D(10^6) x R(10^7), the batch of 256 mocks
+(mocks/s), the roofline of the dominant kernel, and the CPU oracle timed on a
+bounded sample of the headline workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from paper_1911_08275_amd import synth  # noqa: E402
+
+# VALU lane-operation peak of the MI355X: 256 CUs x 64 lanes per clock x 2.4 GHz
+# (the unpacked, unfused vector rate: half of the 78.6 TFLOP/s that counts an
+# FMA as two operations)
+PEAK_LANE_OPS = 256 * 64 * 2.4e9
+OPS_PER_CANDIDATE = 9        # 3 sub, 3 mul, 2 add, 1 compare
+OPS_PER_INRANGE = 2          # bin locate + count
+OPS_PER_INRANGE_WEIGHTED = 12  # binary64 re-evaluation (8), sqrt, w_i*w_j, two sums
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def time_steps(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    stats = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        stats.append(fn())
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    return dt, stats
+
+
+def roofline(cand, inrange_unique, ms_pairs, weighted):
+    ops = OPS_PER_CANDIDATE * cand + (OPS_PER_INRANGE_WEIGHTED if weighted else OPS_PER_INRANGE) \
+        * inrange_unique
+    ach = ops / (ms_pairs * 1e-3) / 1e12
+    peak = PEAK_LANE_OPS / 1e12
+    return {"bound": "alu", "achieved": round(ach, 3), "peak": round(peak, 3),
+            "unit": "TFLOP/s", "frac": round(ach / peak, 4), "traffic": None,
+            "kernel": "k_pairs (pair kernel)", "ops_per_launch": int(ops)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--quick", action="store_true", help="headline workload only")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 256-mock batch")
+    ap.add_argument("--refine", type=str, default=None, help="e.g. 2,2,1")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="also run a plain device copy of known size (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the pair counts "
+              "of this workload fit one MI355X and multi-GPU runs are not part of this build.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    from paper_1911_08275_amd import native
+    native.lib()  # fails loudly when the HIP library is missing
+    refine = tuple(int(v) for v in args.refine.split(",")) if args.refine else None
+    rk = {} if refine is None else {"refine": refine}
+
+    # ---------------------------------------------------------- headline: C2
+    c2 = synth.config2()
+    d2 = native.to_device(c2["cat"])
+    e2 = c2["edges"]
+    log("c2 generated, n =", c2["cat"].n)
+
+    def step(prec):
+        def f():
+            g = native.countpairs_xi(d2, e2, precision=prec, periodic=True, boxsize=420.0,
+                                     need_ravg=True, **rk)
+            return g
+        return f
+
+    dt32, s32 = time_steps(step("fp32"), args.steps, args.warmup)
+    log(f"c2 fp32+recheck: {dt32 * 1e3:.3f} ms/step", s32[-1].stats)
+    dt64, s64 = time_steps(step("fp64"), max(3, args.steps // 2), 1)
+    log(f"c2 fp64: {dt64 * 1e3:.3f} ms/step", s64[-1].stats)
+    g32, g64 = s32[-1], s64[-1]
+    exact = bool((g32.npairs == g64.npairs).all())
+    pairs = int(g32.npairs.sum())                 # ordered in-range pairs
+    ms_pairs32 = float(np.mean([s.stats["ms_pairs"] for s in s32]))
+    ms_pairs64 = float(np.mean([s.stats["ms_pairs"] for s in s64]))
+    st = g32.stats
+    roof = roofline(st["candidates"], pairs // 2, ms_pairs32, True)
+    roof64 = roofline(g64.stats["candidates"], pairs // 2, ms_pairs64, True)
+
+    out = {
+        "metric": "pair evaluations/sec and mocks/sec, FP32+recheck vs FP64, counts bit-exact",
+        "value": pairs / dt32,
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt32 * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "xi(r) auto-count, 1e6 Neyman-Scott points (2e4 parents, "
+                               "Poisson(50) children, sigma 1.5), periodic L=420, 14 log bins "
+                               "0.1-25, weights U(0.5,1.5) with weighted mean r, FP32+FP64 recheck",
+                   "n": c2["cat"].n, "nbins": 14, "rmax": 25.0, "box": 420.0,
+                   "grid": st["grid"], "refine": st["refine"]},
+        "pairs_per_step": pairs,
+        "candidates_per_step": st["candidates"],
+        "candidate_rate": st["candidates"] / dt32,
+        "recheck_fraction": st["rechecks"] / max(1, pairs // 2),
+        "ms_pairs_kernel": ms_pairs32,
+        "ms_grid": float(np.mean([s.stats["ms_grid"] for s in s32])),
+        "fp64": {"value": pairs / dt64, "ms_per_step": dt64 * 1e3, "ms_pairs_kernel": ms_pairs64,
+                 "roofline_frac": roof64["frac"]},
+        "fp32_over_fp64": dt64 / dt32,
+        "counts_equal_fp32_fp64": exact,
+        "roofline": roof,
+    }
+
+    extras = {}
+    if not args.quick:
+        # ------------------------------------------------------ C3: wp 2-D
+        c3 = synth.config3()
+        d3 = native.to_device(c3["cat"])
+        res = {}
+        for prec in ("fp32", "fp64"):
+            dt, ss = time_steps(lambda: native.countpairs_wp(
+                d3, c3["edges"], 40.0, 40, precision=prec, periodic=True, boxsize=420.0, **rk),
+                max(3, args.steps // 2), 1)
+            res[prec] = (dt, ss[-1])
+            log(f"c3 wp {prec}: {dt * 1e3:.3f} ms/step", ss[-1].stats)
+        p3 = int(res["fp32"][1].npairs.sum())
+        extras["wp_c3"] = {"pairs_per_step": p3,
+                           "fp32": {"value": p3 / res["fp32"][0], "ms": res["fp32"][0] * 1e3,
+                                    "ms_pairs_kernel": res["fp32"][1].stats["ms_pairs"]},
+                           "fp64": {"value": p3 / res["fp64"][0], "ms": res["fp64"][0] * 1e3,
+                                    "ms_pairs_kernel": res["fp64"][1].stats["ms_pairs"]},
+                           "counts_equal": bool((res["fp32"][1].npairs ==
+                                                 res["fp64"][1].npairs).all())}
+        del d3
+        # ---------------------------------------------------- C4: cross DR
+        c4 = synth.config4()
+        dd, dr = native.to_device(c4["d"]), native.to_device(c4["r"])
+        res = {}
+        for prec in ("fp32", "fp64"):
+            dt, ss = time_steps(lambda: native.countpairs_cross(
+                dd, dr, c4["edges"], precision=prec, periodic=False, **rk),
+                max(2, args.steps // 3), 1)
+            res[prec] = (dt, ss[-1])
+            log(f"c4 cross {prec}: {dt * 1e3:.3f} ms/step", ss[-1].stats)
+        p4 = int(res["fp32"][1].npairs.sum())
+        extras["cross_c4"] = {"pairs_per_step": p4,
+                              "fp32": {"value": p4 / res["fp32"][0], "ms": res["fp32"][0] * 1e3},
+                              "fp64": {"value": p4 / res["fp64"][0], "ms": res["fp64"][0] * 1e3},
+                              "counts_equal": bool((res["fp32"][1].npairs ==
+                                                    res["fp64"][1].npairs).all())}
+        del dd, dr
+        torch.cuda.empty_cache()
+        # ---------------------------------------------------- C5: 256 mocks
+        if not args.no_batch:
+            specs = synth.mock_specs()
+            t = time.perf_counter()
+            with ThreadPoolExecutor(8) as ex:
+                cats = list(ex.map(synth.mock, specs))
+            log(f"c5 generated {len(cats)} mocks, {sum(c.n for c in cats)} points in "
+                f"{time.perf_counter() - t:.1f}s")
+            devs = [native.to_device(c) for c in cats]
+            del cats
+            xe = synth.log_edges(0.1, 25.0, 14)
+            bres = {}
+            for prec in ("fp32", "fp64"):
+                plan = native.Plan(devs, xi_edges=xe, wp_edges=xe, pimax=40.0, npibins=40,
+                                   precision=prec, periodic=True, boxsize=420.0, **rk)
+                nrep = 2 if prec == "fp32" else 1
+                plan.execute()
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                for _ in range(nrep):
+                    plan.execute()
+                torch.cuda.synchronize()
+                dt = (time.perf_counter() - t) / nrep
+                xi, wp = plan.results()
+                sx, sw = plan.stats()
+                bres[prec] = (dt, xi, wp, sx, sw)
+                log(f"c5 batch {prec}: {dt:.3f} s per evaluation of 256 mocks")
+                plan.close()
+            dt = bres["fp32"][0]
+            pairs5 = int(bres["fp32"][1].sum() + bres["fp32"][2].sum())
+            extras["batch_c5"] = {
+                "mocks": len(devs), "points": int(sum(d.n for d in devs)),
+                "mocks_per_s": len(devs) / dt, "s_per_eval": dt,
+                "pairs_per_eval": pairs5, "pairs_per_s": pairs5 / dt,
+                "fp64_mocks_per_s": len(devs) / bres["fp64"][0],
+                "counts_equal": bool((bres["fp32"][1] == bres["fp64"][1]).all() and
+                                     (bres["fp32"][2] == bres["fp64"][2]).all()),
+                "graph_ms": bres["fp32"][3]["ms_total"],
+                "xi_candidates": bres["fp32"][3]["candidates"],
+                "wp_candidates": bres["fp32"][4]["candidates"]}
+            del devs
+            torch.cuda.empty_cache()
+    if extras:
+        out["extras"] = extras
+
+    if args.copy_calib:
+        # plain copy of a known size, for scaling memory counters
+        a = torch.empty(256 * 1024 * 1024 // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        out["copy_calib_bytes"] = a.numel() * 4
+
+    # ------------------------------------------------- CPU oracle baseline
+    if not args.no_cpu:
+        import oracle
+        rng = np.random.Generator(np.random.PCG64(123))
+        frac = 0.25
+        idx = np.sort(rng.choice(c2["cat"].n, int(frac * c2["cat"].n), replace=False))
+        sub = c2["cat"].subset(idx)
+        t = time.perf_counter()
+        ref = oracle.xi(sub, e2, periodic=True, box=420.0, other=c2["cat"])
+        tcpu = time.perf_counter() - t
+        # the same sample through the GPU cross path must agree exactly
+        gs = native.countpairs_cross(native.to_device(sub), d2, e2, periodic=True, boxsize=420.0,
+                                     need_ravg=True, **rk)
+        same = bool((gs.npairs == ref.npairs).all())
+        rel = float(np.max(np.abs(gs.wsum - ref.wsum) / np.maximum(ref.wsum, 1e-300)))
+        out["cpu_baseline"] = {
+            "value": float(ref.npairs.sum()) / tcpu, "unit": "pairs/s",
+            "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"{len(idx)} random primaries (25%) of the headline catalogue against all "
+                      f"1e6 points (cross count, weighted, periodic); {tcpu:.1f} s",
+            "gpu_matches_oracle_on_sample": same, "wsum_max_rel_err": rel}
+        log(f"cpu oracle: {tcpu:.1f} s on {oracle.num_threads()} threads, match={same}")
+
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

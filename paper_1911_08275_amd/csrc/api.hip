@@ -446,6 +446,7 @@ static int launch_build(hipStream_t st, const PointsDev *d_pts, const GridGeom *
                         const int64_t *d_cell_prefix, const int64_t *d_col_prefix,
                         const int *d_maxspan, int *d_err, bool tiles) {
   const int fb = (int)std::min<int64_t>(std::max<int64_t>((ncell + 255) / 256, 1), 4096);
+  (void)hipGetLastError();
   hipLaunchKernelGGL(k_fill_i32, dim3(fb), dim3(256), 0, st, S.ccount, ncell, 0);
   const int ab = (int)std::min<int64_t>(std::max<int64_t>((n + 255) / 256, 1), 8192);
   if (n > 0)
@@ -495,8 +496,12 @@ static int launch_pairs_t(hipStream_t st, const PairParams &P, size_t lds, int n
   }
   const int per_cu = std::max(1, std::min(8, (int)(160 * 1024 / std::max<size_t>(lds, 1))));
   const int grid = num_cus() * per_cu;
+  (void)hipGetLastError();  // drop any stale error so the check below is about this launch
   hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * nwaves), lds, st, P);
-  return hipGetLastError() == hipSuccess ? CP_OK : fail(CP_ERR_DEVICE, "pair launch failed");
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? CP_OK
+                         : fail(CP_ERR_DEVICE, std::string("pair launch failed: ") +
+                                                   hipGetErrorString(e));
 }
 
 static int launch_pairs(hipStream_t st, int mode, int prec, int w, const PairParams &P,
@@ -1014,6 +1019,7 @@ struct cp_plan {
   hipStream_t cap = nullptr;
   hipGraphExec_t gexec = nullptr;
   bool use_graph = true;
+  int timed = 0;                 // 1: eager events, 2: graph events
   hipEvent_t ev[5] = {};
 };
 
@@ -1176,13 +1182,16 @@ static int batch_enqueue(cp_plan &pl, Batch &b, hipStream_t st) {
   return launch_pairs(st, b.mode, b.prec, 0, b.P, b.lds, b.nwaves);
 }
 
-static int plan_enqueue(cp_plan &pl, hipStream_t st) {
+// Enqueue one evaluation.  With timing events (eager mode only) the xi and
+// wp halves are timed separately; a captured graph is timed as a whole.
+static int plan_enqueue(cp_plan &pl, hipStream_t st, bool events) {
   int rc;
-  HIPCHK(hipEventRecord(pl.ev[0], st));
+  (void)hipGetLastError();
+  if (events) HIPCHK(hipEventRecord(pl.ev[0], st));
   if ((rc = batch_enqueue(pl, pl.xi, st))) return rc;
-  HIPCHK(hipEventRecord(pl.ev[1], st));
+  if (events) HIPCHK(hipEventRecord(pl.ev[1], st));
   if ((rc = batch_enqueue(pl, pl.wp, st))) return rc;
-  HIPCHK(hipEventRecord(pl.ev[2], st));
+  if (events) HIPCHK(hipEventRecord(pl.ev[2], st));
   return CP_OK;
 }
 
@@ -1295,11 +1304,15 @@ int cp_plan_create(const cp_points *mocks, int nmocks, const double *xi_edges, i
 int cp_plan_execute(cp_plan *pl, void *stream) {
   if (!pl) return fail(CP_ERR_INVALID_ARG, "plan is NULL");
   hipStream_t st = (hipStream_t)stream;
-  if (!pl->use_graph) return plan_enqueue(*pl, st);
+  if (!pl->use_graph) {
+    pl->timed = 1;
+    return plan_enqueue(*pl, st, true);
+  }
   if (!pl->gexec) {
     // capture the whole pipeline once on the plan's own stream
+    (void)hipGetLastError();
     HIPCHK(hipStreamBeginCapture(pl->cap, hipStreamCaptureModeThreadLocal));
-    int rc = plan_enqueue(*pl, pl->cap);
+    int rc = plan_enqueue(*pl, pl->cap, false);
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamEndCapture(pl->cap, &graph);
     if (rc) {
@@ -1314,7 +1327,10 @@ int cp_plan_execute(cp_plan *pl, void *stream) {
       return fail(CP_ERR_DEVICE, "graph instantiation failed");
     }
   }
+  HIPCHK(hipEventRecord(pl->ev[3], st));
   HIPCHK(hipGraphLaunch(pl->gexec, st));
+  HIPCHK(hipEventRecord(pl->ev[4], st));
+  pl->timed = 2;
   return CP_OK;
 }
 
@@ -1365,8 +1381,13 @@ int cp_plan_stats(cp_plan *pl, cp_stats *xs, cp_stats *ws) {
       o->refine[a] = b.g.r[a];
     }
     float ms = 0;
-    if (hipEventElapsedTime(&ms, pl->ev[s], pl->ev[s + 1]) == hipSuccess) o->ms_pairs = ms;
-    if (hipEventElapsedTime(&ms, pl->ev[0], pl->ev[2]) == hipSuccess) o->ms_total = ms;
+    if (pl->timed == 1) {
+      if (hipEventElapsedTime(&ms, pl->ev[s], pl->ev[s + 1]) == hipSuccess) o->ms_pairs = ms;
+      if (hipEventElapsedTime(&ms, pl->ev[0], pl->ev[2]) == hipSuccess) o->ms_total = ms;
+    } else if (pl->timed == 2) {
+      if (hipEventElapsedTime(&ms, pl->ev[3], pl->ev[4]) == hipSuccess) o->ms_total = ms;
+    }
+    (void)hipGetLastError();
   }
   return CP_OK;
 }

@@ -196,7 +196,7 @@ struct LanePt {
 
 // xi, binary32 filter.  OWN: the streamed cell is one of the tile's own
 // cells (auto-count): only j > i pairs.
-template <bool OWN, int W>
+template <bool OWN, bool SHIFT, int W>
 __device__ inline void loop_xi_f32(const PairParams &P, WaveArea A, const LanePt &L, int lane,
                                    float rx, float ry, float rz, float ra, int64_t jb, int64_t je,
                                    int64_t pbase, const double S[3], const uint2 *tab32,
@@ -223,27 +223,35 @@ __device__ inline void loop_xi_f32(const PairParams &P, WaveArea A, const LanePt
       } else {
         const double ux = DP[4 * j], uy = DP[4 * j + 1], uz = DP[4 * j + 2];
         double dx, dy, dz;
-        ref_sep<true, false>(L.x, L.y, L.z, ux, uy, uz, S, wrapax, 0.0, 0.0, dx, dy, dz);
+        ref_sep<SHIFT, false>(L.x, L.y, L.z, ux, uy, uz, S, wrapax, 0.0, 0.0, dx, dy, dz);
         const double s64 = (dx * dx + dy * dy) + dz * dz;
         atomicAdd(&A.hist[exact_slot(sE, nb, s64) * 64 + lane], 1u);
         nrechk++;
       }
     } else {
+      // weighted: the binary32 bin stands when certain; the separation
+      // itself is always taken in binary64 for the weighted sum
+      const TabHit h = tab_lookup(tab32, lo, hi, sh, s);
       const double ux = DP[4 * j], uy = DP[4 * j + 1], uz = DP[4 * j + 2], uw = DP[4 * j + 3];
       double dx, dy, dz;
-      ref_sep<true, false>(L.x, L.y, L.z, ux, uy, uz, S, wrapax, 0.0, 0.0, dx, dy, dz);
+      ref_sep<SHIFT, false>(L.x, L.y, L.z, ux, uy, uz, S, wrapax, 0.0, 0.0, dx, dy, dz);
       const double s64 = (dx * dx + dy * dy) + dz * dz;
-      const int slot = slot64(tab64, P.tab64_lo, P.tab64_hi, sh, sE, nb, s64);
+      int slot = h.slot;
+      if (h.unc) {
+        slot = exact_slot(sE, nb, s64);
+        nrechk++;
+      }
       const double ww = L.w * uw;
-      atomicAdd(&A.hist[slot * 64 + lane], 1u);
-      A.hw[slot * 64 + lane] += ww;
-      A.hwr[slot * 64 + lane] += ww * sqrt(s64);
+      const int a = slot * 64 + lane;
+      atomicAdd(&A.hist[a], 1u);
+      atomicAdd(&A.hw[a], ww);
+      atomicAdd(&A.hwr[a], ww * sqrt(s64));
     }
   }
 }
 
 // wp, binary32 filter.
-template <bool OWN, int W>
+template <bool OWN, bool SHIFT, int W>
 __device__ inline void loop_wp_f32(const PairParams &P, WaveArea A, const LanePt &L, int lane,
                                    float rx, float ry, float rz, float ra, int64_t jb, int64_t je,
                                    int64_t pbase, const double S[3], const uint2 *tab32,
@@ -279,7 +287,7 @@ __device__ inline void loop_wp_f32(const PairParams &P, WaveArea A, const LanePt
     if (unc) {
       const double ux = DP[4 * j], uy = DP[4 * j + 1], uz = DP[4 * j + 2], uw = DP[4 * j + 3];
       double dx, dy, dz;
-      ref_sep<true, false>(L.x, L.y, L.z, ux, uy, uz, S, wrapax, 0.0, 0.0, dx, dy, dz);
+      ref_sep<SHIFT, false>(L.x, L.y, L.z, ux, uy, uz, S, wrapax, 0.0, 0.0, dx, dy, dz);
       const double rp2 = dx * dx + dy * dy;
       const double pz64 = fabs(dz);
       if (!W) nrechk++;
@@ -323,8 +331,8 @@ __device__ inline void loop_f64(const PairParams &P, WaveArea A, const LanePt &L
       atomicAdd(&A.hist[slot * 64 + lane], 1u);
       if (W) {
         const double ww = L.w * DP[4 * j + 3];
-        A.hw[slot * 64 + lane] += ww;
-        A.hwr[slot * 64 + lane] += ww * sqrt(s64);
+        atomicAdd(&A.hw[slot * 64 + lane], ww);
+        atomicAdd(&A.hwr[slot * 64 + lane], ww * sqrt(s64));
       }
     } else {
       const double pz64 = fabs(dz);
@@ -552,20 +560,20 @@ __global__ __launch_bounds__(256) void k_pairs(PairParams P) {
           const float rzf = valid ? (float)(L.z - oz) : 1e18f;
           if (MODE == XI) {
             const float ra = __builtin_fmaf(rzf, rzf, __builtin_fmaf(ryf, ryf, rxf * rxf));
-            if (own)
-              loop_xi_f32<true, W>(P, A, L, lane, rxf, ryf, rzf, ra, jb, je, pbase2, S, tab32,
-                                   tab64, sE, nrechk);
-            else
-              loop_xi_f32<false, W>(P, A, L, lane, rxf, ryf, rzf, ra, jb, je, pbase2, S, tab32,
-                                    tab64, sE, nrechk);
+#define CP_XI(O, SH)                                                                      \
+  loop_xi_f32<O, SH, W>(P, A, L, lane, rxf, ryf, rzf, ra, jb, je, pbase2, S, tab32, tab64, sE,  \
+                        nrechk)
+            if (own) { if (shifted) CP_XI(true, true); else CP_XI(true, false); }
+            else { if (shifted) CP_XI(false, true); else CP_XI(false, false); }
+#undef CP_XI
           } else {
             const float ra = __builtin_fmaf(ryf, ryf, rxf * rxf);
-            if (own)
-              loop_wp_f32<true, W>(P, A, L, lane, rxf, ryf, rzf, ra, jb, je, pbase2, S, tab32,
-                                   tab64, sE, nrechk);
-            else
-              loop_wp_f32<false, W>(P, A, L, lane, rxf, ryf, rzf, ra, jb, je, pbase2, S, tab32,
-                                    tab64, sE, nrechk);
+#define CP_WP(O, SH)                                                                      \
+  loop_wp_f32<O, SH, W>(P, A, L, lane, rxf, ryf, rzf, ra, jb, je, pbase2, S, tab32, tab64, sE,  \
+                        nrechk)
+            if (own) { if (shifted) CP_WP(true, true); else CP_WP(true, false); }
+            else { if (shifted) CP_WP(false, true); else CP_WP(false, false); }
+#undef CP_WP
           }
         } else {
           if (anywrap) {
