@@ -58,7 +58,7 @@ static LdsLayout lds_layout_host(int mode, int prec, int weighted, int n32, int 
   const int NS = nb + 2;
   const size_t words = mode == XI ? (size_t)NS * 64 : (size_t)NS * npi;
   L.wave_hist = align16h(words * 4);
-  L.wave_w = weighted ? words * 8 : 0;
+  L.wave_w = weighted ? (mode == XI ? (size_t)NS * kWStripe : words) * 8 : 0;
   L.wave_bytes = L.wave_hist + 2 * L.wave_w;
   return L;
 }
@@ -357,8 +357,9 @@ static void carve_set(Carver &cv, SetBufs &S, int64_t n, int64_t ncell, int64_t 
   S.cstart = cv.take<int>(ncell + 1);
   S.cid = cv.take<int>(n > 0 ? n : 1);
   S.rank = cv.take<int>(n > 0 ? n : 1);
-  S.pos = cv.take<double4>(n > 0 ? n : 1);
-  S.strm = cv.take<float4>(n > 0 ? n : 1);
+  // +8 records: the pair kernels prefetch scalar loads past a cell's end
+  S.pos = cv.take<double4>(n + 8);
+  S.strm = cv.take<float4>(n + 8);
   S.cbox = cv.take<CellBox>(ncell);
   if (want_tiles) {
     S.colcnt = cv.take<int>(ncol + 1);
@@ -521,6 +522,7 @@ static int launch_pairs(hipStream_t st, int mode, int prec, int w, const PairPar
 // Binning setup shared by single calls and plans.
 struct Binning {
   std::vector<double> E;
+  std::vector<float> C32, A32;
   Table t32, t64;
   int shift;
   float AB32;
@@ -559,6 +561,8 @@ static int make_binning(int mode, int prec, const double *edges, int nedges, dou
   }
   if (prec != F32R) B.t32 = B.t64;
   B.AB32 = A32[nb];
+  B.C32 = C32;
+  B.A32 = A32;
   B.dpi = mode == WP ? pimax / npi : 1.0;
   if (mode == WP) {
     const double u = std::ldexp(1.0, -24);
@@ -682,15 +686,19 @@ static int run(const Call &c, uint64_t *npairs, double *wsum, double *ravg) {
   const int n32 = (int)B.t32.e.size(), n64 = (int)B.t64.e.size();
 
   // ---- scratch layout
+  float *d_c32 = nullptr, *d_a32 = nullptr;
   auto layout = [&](Carver &cv, SetBufs &S1, SetBufs &S2, Smalls *&sm, uint2 *&t32, uint2 *&t64,
                     double *&E, unsigned long long *&hist, double *&hw, double *&hwr,
                     unsigned long long *&stats, unsigned long long *&qhead, int *&err) {
+    float *&c32 = d_c32, *&a32 = d_a32;
     carve_set(cv, S1, p1.n, ncell, ncol, true, maxt);
     if (!autoc) carve_set(cv, S2, p2.n, ncell, ncol, false, 0);
     sm = cv.take<Smalls>(1);
     t32 = cv.take<uint2>(n32);
     t64 = cv.take<uint2>(n64);
     E = cv.take<double>(c.nedges);
+    c32 = cv.take<float>(c.nedges);
+    a32 = cv.take<float>(c.nedges);
     hist = cv.take<unsigned long long>(nout);
     hw = cv.take<double>(nout);
     hwr = cv.take<double>(nout);
@@ -753,6 +761,8 @@ static int run(const Call &c, uint64_t *npairs, double *wsum, double *ravg) {
   if (n32) HIPCHK(hipMemcpyAsync(d_t32, B.t32.e.data(), n32 * 8, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(d_t64, B.t64.e.data(), n64 * 8, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(d_E, B.E.data(), c.nedges * 8, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(d_c32, B.C32.data(), c.nedges * 4, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(d_a32, B.A32.data(), c.nedges * 4, hipMemcpyHostToDevice, st));
   hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(256), 0, st, d_hist, (int64_t)nout);
   hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(256), 0, st, d_hw, (int64_t)nout);
   hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(256), 0, st, d_hwr, (int64_t)nout);
@@ -793,6 +803,8 @@ static int run(const Call &c, uint64_t *npairs, double *wsum, double *ravg) {
   P.tab64_hi = B.t64.hi;
   P.tab_shift = B.shift;
   P.E = d_E;
+  P.C32 = d_c32;
+  P.A32 = d_a32;
   P.nb = nb;
   P.nslots = nb + 2;
   P.AB32 = B.AB32;
@@ -811,7 +823,7 @@ static int run(const Call &c, uint64_t *npairs, double *wsum, double *ravg) {
   P.hwr = d_hwr;
   P.stats = d_stats;
   P.hist_stride = nout;
-  const int nwaves = weighted && c.mode == XI ? 2 : 4;
+  const int nwaves = 4;
   const LdsLayout LY = lds_layout_host(c.mode, prec, weighted, n32, n64, nb, npi);
   const size_t lds = LY.common + nwaves * LY.wave_bytes;
   if (lds > 160 * 1024) return fail(CP_ERR_INVALID_ARG, "too many bins for the LDS budget");
@@ -965,6 +977,8 @@ extern "C" size_t countpairs_workspace_size(int kind, int64_t n1, int64_t n2, co
   cv.take<uint2>(4096);
   cv.take<uint2>(4096);
   cv.take<double>(nedges);
+  cv.take<float>(nedges);
+  cv.take<float>(nedges);
   cv.take<unsigned long long>(nout);
   cv.take<double>(nout);
   cv.take<double>(nout);
@@ -997,6 +1011,7 @@ struct Batch {
   SetBufs S{};
   uint2 *d_t32 = nullptr, *d_t64 = nullptr;
   double *d_E = nullptr;
+  float *d_c32 = nullptr, *d_a32 = nullptr;
   unsigned long long *d_hist = nullptr, *d_stats = nullptr;
   double *d_hw = nullptr, *d_hwr = nullptr;
   int *d_err = nullptr;
@@ -1082,8 +1097,8 @@ static void batch_carve(Carver &cv, cp_plan &pl, Batch &b) {
   b.S.cstart = cv.take<int>(b.ncell_tot + nm);
   b.S.cid = cv.take<int>(std::max<int64_t>(b.npts_tot, 1));
   b.S.rank = cv.take<int>(std::max<int64_t>(b.npts_tot, 1));
-  b.S.pos = cv.take<double4>(std::max<int64_t>(b.npts_tot, 1));
-  b.S.strm = cv.take<float4>(std::max<int64_t>(b.npts_tot, 1));
+  b.S.pos = cv.take<double4>(b.npts_tot + 8);
+  b.S.strm = cv.take<float4>(b.npts_tot + 8);
   b.S.cbox = cv.take<CellBox>(b.ncell_tot);
   b.S.colcnt = cv.take<int>(b.ncol_tot + 1);
   b.S.coloff = cv.take<int>(b.ncol_tot + 1);
@@ -1091,6 +1106,8 @@ static void batch_carve(Carver &cv, cp_plan &pl, Batch &b) {
   b.d_t32 = cv.take<uint2>(b.B.t32.e.size());
   b.d_t64 = cv.take<uint2>(b.B.t64.e.size());
   b.d_E = cv.take<double>(b.nb + 1);
+  b.d_c32 = cv.take<float>(b.nb + 1);
+  b.d_a32 = cv.take<float>(b.nb + 1);
   b.d_hist = cv.take<unsigned long long>((int64_t)b.nout * nm);
   b.d_hw = cv.take<double>(1);
   b.d_hwr = cv.take<double>(1);
@@ -1111,6 +1128,8 @@ static int batch_upload(cp_plan &pl, Batch &b) {
     HIPCHK(hipMemcpy(b.d_t32, b.B.t32.e.data(), 8 * b.B.t32.e.size(), hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(b.d_t64, b.B.t64.e.data(), 8 * b.B.t64.e.size(), hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(b.d_E, b.B.E.data(), 8 * (b.nb + 1), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(b.d_c32, b.B.C32.data(), 4 * (b.nb + 1), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(b.d_a32, b.B.A32.data(), 4 * (b.nb + 1), hipMemcpyHostToDevice));
   PairParams &P = b.P;
   memset(&P, 0, sizeof(P));
   P.tiles = b.S.tiles;
@@ -1131,6 +1150,8 @@ static int batch_upload(cp_plan &pl, Batch &b) {
   P.tab64_hi = b.B.t64.hi;
   P.tab_shift = b.B.shift;
   P.E = b.d_E;
+  P.C32 = b.d_c32;
+  P.A32 = b.d_a32;
   P.nb = b.nb;
   P.nslots = b.nb + 2;
   P.AB32 = b.B.AB32;

@@ -12,6 +12,7 @@ constexpr int kMaxAxisCells = 1023; // cells per axis (packed in 10 bits)
 constexpr int kMaxBins = 60;        // separation bins; slots 0 and nb+1 are trash and
                                     // slot + 1 must fit the 6-bit table code
 constexpr int kMaxPiBins = 256;
+constexpr int kWStripe = 8;       // copies of each weight sum per wave (lane & 7)
 
 enum Mode { XI = 0, WP = 1 };
 enum Prec { F64 = 0, F32R = 1 };
@@ -82,6 +83,8 @@ struct PairParams {
   int tab32_lo, tab32_hi, tab64_lo, tab64_hi;
   int tab_shift;
   const double *E;           // squared edges, nb + 1
+  const float *C32, *A32;    // binary32 band of each edge: v < C proves s < E,
+                             // v >= A proves s >= E (nb + 1 each)
   int nb;                    // separation bins
   int nslots;                // nb + 2
   float AB32;                // binary32 s~ >= AB32 -> certainly >= E_B

@@ -243,59 +243,40 @@ __global__ __launch_bounds__(256) void k_cellbox(const GridGeom *geom, int nmock
 
 // ------------------------------------------------------------------ tiles
 
-// Greedy packing of each column's z-run of cells into tiles of <= 64
-// points and <= maxspan cells; a cell with more than 64 points is split into
-// chunks of 64.  emit = 0: count tiles per column; emit = 1: write them at
-// the offsets of the scanned counts.
+// Packing of each column's z-run of points into tiles: consecutive runs of
+// at most 64 points (cells may be cut anywhere) whose cells span at most
+// maxspan z-cells, so every lane holds a point whenever the column allows.
+// emit = 0: count tiles per column; emit = 1: write them at the offsets of
+// the scanned counts.
 __device__ inline void walk_column(const GridGeom &G, const int *cstart, int col, int maxspan,
                                    int mock, int emit, Tile *out, int64_t &ntile) {
   const int nz = G.n[2];
-  int cur_n = 0, cz0 = -1;
-  int64_t cur_p0 = 0;
-  auto close = [&](int cz1) {
-    if (cz0 >= 0 && cur_n > 0) {
-      if (emit) {
-        Tile T;
-        T.p0 = G.pbase + cur_p0;
-        T.n = cur_n;
-        T.mock = mock;
-        T.col = col;
-        T.cz0 = cz0;
-        T.cz1 = cz1;
-        T.pad = 0;
-        out[ntile] = T;
-      }
-      ntile++;
+  const int c0 = col * nz;
+  const int pend = cstart[G.sbase + c0 + nz];
+  int p = cstart[G.sbase + c0];
+  int z = 0;   // cell of point p
+  while (p < pend) {
+    while (cstart[G.sbase + c0 + z + 1] <= p) z++;
+    // furthest cell allowed by the span limit, and its end
+    const int zmax = min(nz - 1, z + maxspan - 1);
+    const int lim = cstart[G.sbase + c0 + zmax + 1];
+    const int q = min(p + kTileMax, lim);
+    int z1 = z;
+    while (cstart[G.sbase + c0 + z1 + 1] < q) z1++;
+    if (emit) {
+      Tile T;
+      T.p0 = G.pbase + p;
+      T.n = q - p;
+      T.mock = mock;
+      T.col = col;
+      T.cz0 = z;
+      T.cz1 = z1;
+      T.pad = 0;
+      out[ntile] = T;
     }
-    cur_n = 0;
-    cz0 = -1;
-  };
-  int last = -1;
-  for (int z = 0; z < nz; z++) {
-    const int c = col * nz + z;
-    const int b = cstart[G.sbase + c], e = cstart[G.sbase + c + 1];
-    const int n = e - b;
-    if (n == 0) continue;
-    if (n > kTileMax) {
-      close(last);
-      for (int q = b; q < e; q += kTileMax) {
-        cz0 = z;
-        cur_p0 = q;
-        cur_n = (e - q) < kTileMax ? (e - q) : kTileMax;
-        close(z);
-      }
-      last = z;
-      continue;
-    }
-    if (cz0 >= 0 && (cur_n + n > kTileMax || z - cz0 + 1 > maxspan)) close(last);
-    if (cz0 < 0) {
-      cz0 = z;
-      cur_p0 = b;
-    }
-    cur_n += n;
-    last = z;
+    ntile++;
+    p = q;
   }
-  close(last);
 }
 
 __global__ __launch_bounds__(256) void k_tiles(const GridGeom *geom, int nmock,

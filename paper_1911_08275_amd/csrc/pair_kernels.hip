@@ -88,7 +88,7 @@ struct TabHit {
 };
 __device__ inline TabHit tab_lookup(const uint2 *tab, int lo, int hi, int sh, float v) {
   int b = __float_as_int(v) >> sh;
-  b = b < lo ? lo : (b > hi ? hi : b);
+  b = min(max(b, lo), hi);
   const uint2 e = tab[b - lo];
   const bool ch = v >= __uint_as_float(e.y);
   TabHit h;
@@ -103,6 +103,18 @@ __device__ inline int slot64(const uint2 *tab, int lo, int hi, int sh, const dou
   TabHit h = tab_lookup(tab, lo, hi, sh, (float)s);
   if (h.unc) h.slot = exact_slot(E, nb, s);
   return h.slot;
+}
+
+// Square root for the weighted mean separation (not part of any bin
+// decision): the hardware reciprocal square root (relative error ~5e-8 on
+// gfx950) refined by one Newton step in binary64, measured relative error
+// below 5e-15, far inside the 1e-12 tolerance of the weighted sums.
+__device__ inline double sep_sqrt(double x) {
+  if (!(x > 0.0)) return 0.0;
+  const double y = __builtin_amdgcn_rsq(x);
+  const double r = x * y;
+  const double e = __builtin_fma(-r, r, x);
+  return __builtin_fma(0.5 * y, e, r);
 }
 
 // Reference separation of the tile point (px, py, pz) and streamed point q
@@ -145,20 +157,23 @@ __device__ inline void flush_hist(const PairParams &P, WaveArea A, int mock, int
     for (int s = 1; s <= nb; s++) {
       unsigned long long v = wave_sum_u64((unsigned long long)A.hist[s * 64 + lane]);
       if (lane == 0 && v) atomicAdd(gh + (s - 1), v);
-      if (W) {
-        double a = wave_sum_f64(A.hw[s * 64 + lane]);
-        double b = wave_sum_f64(A.hwr[s * 64 + lane]);
-        if (lane == 0) {
-          unsafeAtomicAdd(P.hw + (int64_t)mock * P.hist_stride + (s - 1), a);
-          unsafeAtomicAdd(P.hwr + (int64_t)mock * P.hist_stride + (s - 1), b);
-        }
-      }
     }
-    for (int s = 0; s < NS; s++) {
-      A.hist[s * 64 + lane] = 0u;
-      if (W) {
-        A.hw[s * 64 + lane] = 0.0;
-        A.hwr[s * 64 + lane] = 0.0;
+    if (W && lane >= 1 && lane <= nb) {
+      double a = 0.0, b = 0.0;
+      for (int c = 0; c < kWStripe; c++) {
+        a += A.hw[lane * kWStripe + c];
+        b += A.hwr[lane * kWStripe + c];
+      }
+      if (a != 0.0) unsafeAtomicAdd(P.hw + (int64_t)mock * P.hist_stride + (lane - 1), a);
+      if (b != 0.0) unsafeAtomicAdd(P.hwr + (int64_t)mock * P.hist_stride + (lane - 1), b);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    for (int s = 0; s < NS; s++) A.hist[s * 64 + lane] = 0u;
+    if (W) {
+      for (int t = lane; t < NS * kWStripe; t += 64) {
+        A.hw[t] = 0.0;
+        A.hwr[t] = 0.0;
       }
     }
   } else {
@@ -192,163 +207,480 @@ struct LanePt {
   int iloc;   // sorted index relative to the catalogue (own-cell ordering)
 };
 
+// ------------------------------------------------------------- streaming
+//
+// A unit's records [jb, je) are walked through the scalar cache in groups,
+// each group's loads issued one group ahead.  The main loop handles two
+// groups per trip so the two buffers alternate without copies; the stream
+// arrays are padded by 8 records, so the look-ahead never leaves the
+// allocation.  The body is called once per record with its values in SGPRs.
+
+__device__ inline bool wave_any(bool p) { return __ballot(p) != 0ull; }
+
+#define CP_LOAD16(dst, src)                                                                    \
+  _Pragma("unroll") for (int t_ = 0; t_ < 16; t_++) dst[t_] = (src)[t_];
+#define CP_REC4(arr, jj, u) body((jj) + (u), arr[4 * (u)], arr[4 * (u) + 1], arr[4 * (u) + 2], \
+                                 arr[4 * (u) + 3])
+
+template <typename F>
+__device__ inline void stream_f32(const float4 *base, int jb, int je, F &&body) {
+  sfloat *p = (sfloat *)(base + jb);
+  int j = jb;
+  float a[16];
+  CP_LOAD16(a, p);
+  while (j + 8 <= je) {
+    float b[16];
+    CP_LOAD16(b, p + 16);
+    CP_REC4(a, j, 0); CP_REC4(a, j, 1); CP_REC4(a, j, 2); CP_REC4(a, j, 3);
+    CP_LOAD16(a, p + 32);
+    CP_REC4(b, j + 4, 0); CP_REC4(b, j + 4, 1); CP_REC4(b, j + 4, 2); CP_REC4(b, j + 4, 3);
+    j += 8;
+    p += 32;
+  }
+  if (j < je) {
+    float b[16];
+    CP_LOAD16(b, p + 16);
+#pragma unroll
+    for (int u = 0; u < 4; u++)
+      if (j + u < je) CP_REC4(a, j, u);
+#pragma unroll
+    for (int u = 0; u < 4; u++)
+      if (j + 4 + u < je) CP_REC4(b, j + 4, u);
+  }
+}
+
+// binary64 records only (x, y, z, w), groups of two.
+#define CP_LOAD8D(dst, src)                                                                    \
+  _Pragma("unroll") for (int t_ = 0; t_ < 8; t_++) dst[t_] = (src)[t_];
+#define CP_REC2D(arr, jj, u) body((jj) + (u), arr[4 * (u)], arr[4 * (u) + 1], arr[4 * (u) + 2], \
+                                  arr[4 * (u) + 3])
+template <typename F>
+__device__ inline void stream_f64(const double4 *base, int jb, int je, F &&body) {
+  sdouble *p = (sdouble *)(base + jb);
+  int j = jb;
+  double a[8];
+  CP_LOAD8D(a, p);
+  while (j + 4 <= je) {
+    double b[8];
+    CP_LOAD8D(b, p + 8);
+    CP_REC2D(a, j, 0); CP_REC2D(a, j, 1);
+    CP_LOAD8D(a, p + 16);
+    CP_REC2D(b, j + 2, 0); CP_REC2D(b, j + 2, 1);
+    j += 4;
+    p += 16;
+  }
+  if (j < je) {
+    double b[8];
+    CP_LOAD8D(b, p + 8);
+    if (j < je) CP_REC2D(a, j, 0);
+    if (j + 1 < je) CP_REC2D(a, j, 1);
+    if (j + 2 < je) CP_REC2D(b, j + 2, 0);
+    if (j + 3 < je) CP_REC2D(b, j + 2, 1);
+  }
+}
+
+// binary32 and binary64 records together (weighted loops), groups of two.
+#define CP_RECW(fa, da, jj, u)                                                                 \
+  body((jj) + (u), fa[4 * (u)], fa[4 * (u) + 1], fa[4 * (u) + 2], fa[4 * (u) + 3], da[4 * (u)],  \
+       da[4 * (u) + 1], da[4 * (u) + 2], da[4 * (u) + 3])
+template <typename F>
+__device__ inline void stream_w(const float4 *fbase, const double4 *dbase, int jb, int je,
+                                F &&body) {
+  sfloat *p = (sfloat *)(fbase + jb);
+  sdouble *q = (sdouble *)(dbase + jb);
+  int j = jb;
+  float fa[8];
+  double da[8];
+#pragma unroll
+  for (int t = 0; t < 8; t++) {
+    fa[t] = p[t];
+    da[t] = q[t];
+  }
+  while (j + 4 <= je) {
+    float fb[8];
+    double db[8];
+#pragma unroll
+    for (int t = 0; t < 8; t++) {
+      fb[t] = p[8 + t];
+      db[t] = q[8 + t];
+    }
+    CP_RECW(fa, da, j, 0); CP_RECW(fa, da, j, 1);
+#pragma unroll
+    for (int t = 0; t < 8; t++) {
+      fa[t] = p[16 + t];
+      da[t] = q[16 + t];
+    }
+    CP_RECW(fb, db, j + 2, 0); CP_RECW(fb, db, j + 2, 1);
+    j += 4;
+    p += 16;
+    q += 16;
+  }
+  if (j < je) {
+    float fb[8];
+    double db[8];
+#pragma unroll
+    for (int t = 0; t < 8; t++) {
+      fb[t] = p[8 + t];
+      db[t] = q[8 + t];
+    }
+    if (j < je) CP_RECW(fa, da, j, 0);
+    if (j + 1 < je) CP_RECW(fa, da, j, 1);
+    if (j + 2 < je) CP_RECW(fb, db, j + 2, 0);
+    if (j + 3 < je) CP_RECW(fb, db, j + 2, 1);
+  }
+}
+
+// Per-unit data handed to the inner loops.
+struct Unit {
+  int jb, je;             // streamed records, relative to the catalogue's first point
+  const float4 *strm;     // stream / positions of the catalogue (index 0 = its first point)
+  const double4 *pos;
+  double S[3];
+  int slot_lo, slot_hi;   // every pair of the unit lands in [slot_lo, slot_hi]
+};
+
+__device__ inline float gram3(float rx, float ry, float rz, float ra, float qx, float qy, float qz,
+                              float qw) {
+  float v = __builtin_fmaf(rx, qx, ra);
+  v = __builtin_fmaf(ry, qy, v);
+  v = __builtin_fmaf(rz, qz, v);
+  return v + qw;
+}
+
 // ---------------------------------------------------------------- FP32 loops
 
-// xi, binary32 filter.  OWN: the streamed cell is one of the tile's own
-// cells (auto-count): only j > i pairs.
-template <bool OWN, bool SHIFT, int W>
-__device__ inline void loop_xi_f32(const PairParams &P, WaveArea A, const LanePt &L, int lane,
-                                   float rx, float ry, float rz, float ra, int64_t jb, int64_t je,
-                                   int64_t pbase, const double S[3], const uint2 *tab32,
-                                   const uint2 *tab64, const double *sE, uint32_t &nrechk) {
-  sfloat *SP = (sfloat *)P.strm2;
-  sdouble *DP = (sdouble *)P.pos2;
-  const float AB = P.AB32;
-  const int lo = P.tab32_lo, hi = P.tab32_hi, sh = P.tab_shift;
+// xi, binary32, a unit whose pairs can only land in slot_lo or slot_hi:
+// edge E_t (t = slot_lo) decides; two compares per pair into per-lane
+// counters.  Runs with exec = valid lanes.
+template <bool SHIFT>
+__device__ inline void loop_xi_f32_two(const PairParams &P, WaveArea A, const LanePt &L, int lane,
+                                       float rx, float ry, float rz, float ra, const Unit &U,
+                                       const double *sE, uint32_t &nrechk) {
+  const int t = U.slot_lo;
+  const float Ct = P.C32[t], At = P.A32[t];
   const int nb = P.nb;
   const int wrapax[3] = {0, 0, 0};
-  for (int64_t j = jb; j < je; ++j) {
-    const float qx = SP[4 * j], qy = SP[4 * j + 1], qz = SP[4 * j + 2], qw = SP[4 * j + 3];
-    float t = __builtin_fmaf(rx, qx, ra);
-    t = __builtin_fmaf(ry, qy, t);
-    t = __builtin_fmaf(rz, qz, t);
-    const float s = t + qw;
-    bool inr = s < AB;
-    if (OWN) inr = inr && ((int)(j - pbase) > L.iloc);
-    if (!inr) continue;
-    if (!W) {
-      const TabHit h = tab_lookup(tab32, lo, hi, sh, s);
-      if (!h.unc) {
-        atomicAdd(&A.hist[h.slot * 64 + lane], 1u);
-      } else {
+  uint32_t clo = 0, chi = 0;
+  stream_f32(U.strm, U.jb, U.je, [&](int j, float qx, float qy, float qz, float qw) {
+    const float s = gram3(rx, ry, rz, ra, qx, qy, qz, qw);
+    const bool lo = s < Ct, hi = s >= At;
+    clo += lo ? 1u : 0u;
+    chi += hi ? 1u : 0u;
+    const bool unc = !(lo || hi);
+    if (wave_any(unc)) {
+      if (unc) {
+        sdouble *DP = (sdouble *)U.pos;
         const double ux = DP[4 * j], uy = DP[4 * j + 1], uz = DP[4 * j + 2];
         double dx, dy, dz;
-        ref_sep<SHIFT, false>(L.x, L.y, L.z, ux, uy, uz, S, wrapax, 0.0, 0.0, dx, dy, dz);
+        ref_sep<SHIFT, false>(L.x, L.y, L.z, ux, uy, uz, U.S, wrapax, 0.0, 0.0, dx, dy, dz);
         const double s64 = (dx * dx + dy * dy) + dz * dz;
         atomicAdd(&A.hist[exact_slot(sE, nb, s64) * 64 + lane], 1u);
         nrechk++;
       }
-    } else {
-      // weighted: the binary32 bin stands when certain; the separation
-      // itself is always taken in binary64 for the weighted sum
-      const TabHit h = tab_lookup(tab32, lo, hi, sh, s);
-      const double ux = DP[4 * j], uy = DP[4 * j + 1], uz = DP[4 * j + 2], uw = DP[4 * j + 3];
-      double dx, dy, dz;
-      ref_sep<SHIFT, false>(L.x, L.y, L.z, ux, uy, uz, S, wrapax, 0.0, 0.0, dx, dy, dz);
-      const double s64 = (dx * dx + dy * dy) + dz * dz;
-      int slot = h.slot;
-      if (h.unc) {
-        slot = exact_slot(sE, nb, s64);
+    }
+  });
+  if (U.slot_lo >= 1) atomicAdd(&A.hist[U.slot_lo * 64 + lane], clo);
+  if (U.slot_hi <= nb) atomicAdd(&A.hist[U.slot_hi * 64 + lane], chi);
+}
+
+// Weighted xi, binary32 filter, two-slot unit.  Weight sums of the unit stay
+// in registers (sums of w_j and w_j r per slot; w_i is applied once at the
+// end) and are added to the wave's shared sums when the unit is done.
+// exec = valid lanes.
+template <bool SHIFT>
+__device__ inline void loop_xi_f32_two_w(const PairParams &P, WaveArea A, const LanePt &L,
+                                         int lane, float rx, float ry, float rz, float ra,
+                                         const Unit &U, const double *sE, uint32_t &nrechk) {
+  const int t = U.slot_lo;
+  const float Ct = P.C32[t], At = P.A32[t];
+  const double Et = sE[t];
+  const int nb = P.nb;
+  const bool lo_real = U.slot_lo >= 1, hi_real = U.slot_hi <= nb;
+  // a pair can land in a counted slot: any pair when both slots are bins,
+  // otherwise only pairs that are not certainly in the upper slot
+  const float Acut = hi_real ? 3.0e38f : At;
+  const int wrapax[3] = {0, 0, 0};
+  uint32_t clo = 0, chi = 0;
+  double wlo = 0, whi = 0, rlo = 0, rhi = 0;
+  stream_w(U.strm, U.pos, U.jb, U.je,
+           [&](int j, float qx, float qy, float qz, float qw, double ux, double uy, double uz,
+               double uw) {
+             const float s = gram3(rx, ry, rz, ra, qx, qy, qz, qw);
+             const bool m = s < Acut;
+             if (!wave_any(m)) return;
+             double dx, dy, dz;
+             ref_sep<SHIFT, false>(L.x, L.y, L.z, ux, uy, uz, U.S, wrapax, 0.0, 0.0, dx, dy, dz);
+             bool hi = s >= At;
+             const bool unc = m && !(s < Ct) && !hi;
+             if (wave_any(unc)) {
+               const double s64 = (dx * dx + dy * dy) + dz * dz;
+               if (unc) {
+                 hi = s64 >= Et;
+                 nrechk++;
+               }
+             }
+             const bool counted = m && (hi_real || !hi);
+             const double sw = __builtin_fma(dx, dx, __builtin_fma(dy, dy, dz * dz));
+             const double wj = counted ? uw : 0.0;
+             const double wr = wj * sep_sqrt(sw);
+             if (hi_real) {
+               const bool h = hi && counted;
+               chi += h ? 1u : 0u;
+               clo += (counted && !h) ? 1u : 0u;
+               whi += h ? wj : 0.0;
+               rhi += h ? wr : 0.0;
+               wlo += h ? 0.0 : wj;
+               rlo += h ? 0.0 : wr;
+             } else {
+               clo += counted ? 1u : 0u;
+               wlo += wj;
+               rlo += wr;
+             }
+           });
+  if (lo_real) {
+    atomicAdd(&A.hist[U.slot_lo * 64 + lane], clo);
+    atomicAdd(&A.hw[U.slot_lo * kWStripe + (lane & (kWStripe - 1))], L.w * wlo);
+    atomicAdd(&A.hwr[U.slot_lo * kWStripe + (lane & (kWStripe - 1))], L.w * rlo);
+  }
+  if (hi_real) {
+    atomicAdd(&A.hist[U.slot_hi * 64 + lane], chi);
+    atomicAdd(&A.hw[U.slot_hi * kWStripe + (lane & (kWStripe - 1))], L.w * whi);
+    atomicAdd(&A.hwr[U.slot_hi * kWStripe + (lane & (kWStripe - 1))], L.w * rhi);
+  }
+}
+
+// xi, binary32, general unit: per-lane table lookup.  OWN: one of the tile's
+// own cells (auto-count), only j > i pairs.
+template <bool OWN, bool SHIFT>
+__device__ inline void loop_xi_f32(const PairParams &P, WaveArea A, const LanePt &L, int lane,
+                                   float rx, float ry, float rz, float ra, const Unit &U,
+                                   const uint2 *tab32, const double *sE, uint32_t &nrechk) {
+  const float AB = P.AB32;
+  const int lo = P.tab32_lo, hi = P.tab32_hi, sh = P.tab_shift;
+  const int nb = P.nb;
+  const int wrapax[3] = {0, 0, 0};
+  stream_f32(U.strm, U.jb, U.je, [&](int j, float qx, float qy, float qz, float qw) {
+    const float s = gram3(rx, ry, rz, ra, qx, qy, qz, qw);
+    bool inr = s < AB;
+    if (OWN) inr = inr && (j > L.iloc);
+    if (!wave_any(inr)) return;
+    const TabHit h = tab_lookup(tab32, lo, hi, sh, s);
+    const bool unc = inr && h.unc;
+    // out-of-range and uncertain lanes add to the unused slot 0
+    atomicAdd(&A.hist[((inr && !h.unc) ? h.slot : 0) * 64 + lane], 1u);
+    if (wave_any(unc)) {
+      if (unc) {
+        sdouble *DP = (sdouble *)U.pos;
+        const double ux = DP[4 * j], uy = DP[4 * j + 1], uz = DP[4 * j + 2];
+        double dx, dy, dz;
+        ref_sep<SHIFT, false>(L.x, L.y, L.z, ux, uy, uz, U.S, wrapax, 0.0, 0.0, dx, dy, dz);
+        const double s64 = (dx * dx + dy * dy) + dz * dz;
+        atomicAdd(&A.hist[exact_slot(sE, nb, s64) * 64 + lane], 1u);
         nrechk++;
       }
-      const double ww = L.w * uw;
-      const int a = slot * 64 + lane;
-      atomicAdd(&A.hist[a], 1u);
-      atomicAdd(&A.hw[a], ww);
-      atomicAdd(&A.hwr[a], ww * sqrt(s64));
     }
-  }
+  });
+}
+
+// Weighted xi, binary32 filter, general unit.
+template <bool OWN, bool SHIFT>
+__device__ inline void loop_xi_f32_w(const PairParams &P, WaveArea A, const LanePt &L, int lane,
+                                     float rx, float ry, float rz, float ra, const Unit &U,
+                                     const uint2 *tab32, const double *sE, uint32_t &nrechk) {
+  const float AB = P.AB32;
+  const int lo = P.tab32_lo, hi = P.tab32_hi, sh = P.tab_shift;
+  const int nb = P.nb;
+  const int wrapax[3] = {0, 0, 0};
+  stream_w(U.strm, U.pos, U.jb, U.je,
+           [&](int j, float qx, float qy, float qz, float qw, double ux, double uy, double uz,
+               double uw) {
+             const float s = gram3(rx, ry, rz, ra, qx, qy, qz, qw);
+             bool inr = s < AB;
+             if (OWN) inr = inr && (j > L.iloc);
+             if (!wave_any(inr)) return;
+             const TabHit h = tab_lookup(tab32, lo, hi, sh, s);
+             double dx, dy, dz;
+             ref_sep<SHIFT, false>(L.x, L.y, L.z, ux, uy, uz, U.S, wrapax, 0.0, 0.0, dx, dy, dz);
+             int slot = h.slot;
+             if (wave_any(inr && h.unc)) {
+               if (inr && h.unc) {
+                 const double s64 = (dx * dx + dy * dy) + dz * dz;
+                 slot = exact_slot(sE, nb, s64);
+                 nrechk++;
+               }
+             }
+             const double sw = __builtin_fma(dx, dx, __builtin_fma(dy, dy, dz * dz));
+             const double wr = sep_sqrt(sw);
+             if (inr) {
+               const double ww = L.w * uw;
+               atomicAdd(&A.hist[slot * 64 + lane], 1u);
+               atomicAdd(&A.hw[slot * kWStripe + (lane & (kWStripe - 1))], ww);
+               atomicAdd(&A.hwr[slot * kWStripe + (lane & (kWStripe - 1))], ww * wr);
+             }
+           });
 }
 
 // wp, binary32 filter.
 template <bool OWN, bool SHIFT, int W>
 __device__ inline void loop_wp_f32(const PairParams &P, WaveArea A, const LanePt &L, int lane,
-                                   float rx, float ry, float rz, float ra, int64_t jb, int64_t je,
-                                   int64_t pbase, const double S[3], const uint2 *tab32,
-                                   const uint2 *tab64, const double *sE, uint32_t &nrechk) {
-  sfloat *SP = (sfloat *)P.strm2;
-  sdouble *DP = (sdouble *)P.pos2;
+                                   float rx, float ry, float rz, float ra, const Unit &U,
+                                   const uint2 *tab32, const double *sE, uint32_t &nrechk) {
   const float AB = P.AB32, PIHI = P.pi_hi32, PILO = P.pi_lo32, invd = P.inv_dpi32,
               dlt = P.pi_delta;
   const int lo = P.tab32_lo, hi = P.tab32_hi, sh = P.tab_shift;
   const int nb = P.nb, npi = P.npi;
   const int wrapax[3] = {0, 0, 0};
-  for (int64_t j = jb; j < je; ++j) {
-    const float qx = SP[4 * j], qy = SP[4 * j + 1], qz = SP[4 * j + 2], qw = SP[4 * j + 3];
-    float t = __builtin_fmaf(rx, qx, ra);
-    t = __builtin_fmaf(ry, qy, t);
-    const float s = t + qw;
+  stream_f32(U.strm, U.jb, U.je, [&](int j, float qx, float qy, float qz, float qw) {
+    float v = __builtin_fmaf(rx, qx, ra);
+    v = __builtin_fmaf(ry, qy, v);
+    const float s = v + qw;
     const float pz = fabsf(qz - rz);
     bool inr = (s < AB) && (pz < PIHI);
-    if (OWN) inr = inr && ((int)(j - pbase) > L.iloc);
-    if (!inr) continue;
-    bool unc = true;
-    int slot = 0, l = 0;
+    if (OWN) inr = inr && (j > L.iloc);
+    if (!wave_any(inr)) return;
+    const TabHit h = tab_lookup(tab32, lo, hi, sh, s);
+    const float f = pz * invd;
+    const float fl = floorf(f);
+    const float fr = f - fl;
+    const int l = min((int)fl, npi - 1);
+    const bool unc = inr && (h.unc || (fr < dlt) || (fr > 1.0f - dlt) || (pz >= PILO));
     if (!W) {
-      const TabHit h = tab_lookup(tab32, lo, hi, sh, s);
-      const float f = pz * invd;
-      const float fl = floorf(f);
-      const float fr = f - fl;
-      l = min((int)fl, npi - 1);
-      slot = h.slot;
-      unc = h.unc || (fr < dlt) || (fr > 1.0f - dlt) || (pz >= PILO);
-      if (!unc) atomicAdd(&A.hist[slot * npi + l], 1u);
+      if (inr && !unc) atomicAdd(&A.hist[h.slot * npi + l], 1u);
+      if (!wave_any(unc)) return;
     }
-    if (unc) {
+    if (unc || (W && inr)) {
+      sdouble *DP = (sdouble *)U.pos;
       const double ux = DP[4 * j], uy = DP[4 * j + 1], uz = DP[4 * j + 2], uw = DP[4 * j + 3];
       double dx, dy, dz;
-      ref_sep<SHIFT, false>(L.x, L.y, L.z, ux, uy, uz, S, wrapax, 0.0, 0.0, dx, dy, dz);
-      const double rp2 = dx * dx + dy * dy;
-      const double pz64 = fabs(dz);
-      if (!W) nrechk++;
-      if (pz64 < P.pimax && rp2 < P.EB) {
-        const int sl = W ? slot64(tab64, P.tab64_lo, P.tab64_hi, sh, sE, nb, rp2)
-                         : exact_slot(sE, nb, rp2);
-        const int ll = exact_pibin(pz64, P.dpi, npi);
+      ref_sep<SHIFT, false>(L.x, L.y, L.z, ux, uy, uz, U.S, wrapax, 0.0, 0.0, dx, dy, dz);
+      int sl = h.slot, ll = l;
+      bool keep = true;
+      if (unc) {
+        nrechk++;
+        const double rp2 = dx * dx + dy * dy;
+        const double pz64 = fabs(dz);
+        keep = pz64 < P.pimax && rp2 < P.EB;
+        sl = exact_slot(sE, nb, rp2);
+        ll = exact_pibin(pz64, P.dpi, npi);
+        if (!W && keep) atomicAdd(&A.hist[sl * npi + ll], 1u);
+      }
+      if (W && keep) {
+        const double ww = L.w * uw;
         atomicAdd(&A.hist[sl * npi + ll], 1u);
-        if (W) {
-          const double ww = L.w * uw;
-          atomicAdd(&A.hw[sl * npi + ll], ww);
-          atomicAdd(&A.hwr[sl * npi + ll], ww * sqrt(rp2));
-        }
+        atomicAdd(&A.hw[sl * npi + ll], ww);
+        atomicAdd(&A.hwr[sl * npi + ll], ww * sep_sqrt(__builtin_fma(dx, dx, dy * dy)));
       }
     }
-  }
+  });
 }
 
 // ---------------------------------------------------------------- FP64 loops
 
+// xi, binary64, two-slot unit: one exact compare per pair.  exec = valid lanes.
+template <bool SHIFT>
+__device__ inline void loop_xi_f64_two(const PairParams &P, WaveArea A, const LanePt &L, int lane,
+                                       const Unit &U, const double *sE) {
+  const double Et = sE[U.slot_lo];
+  const int nb = P.nb;
+  const int wrapax[3] = {0, 0, 0};
+  uint32_t chi = 0;
+  stream_f64(U.pos, U.jb, U.je, [&](int j, double ux, double uy, double uz, double uw) {
+    double dx, dy, dz;
+    ref_sep<SHIFT, false>(L.x, L.y, L.z, ux, uy, uz, U.S, wrapax, 0.0, 0.0, dx, dy, dz);
+    const double s64 = (dx * dx + dy * dy) + dz * dz;
+    chi += s64 >= Et ? 1u : 0u;
+  });
+  const uint32_t clo = (uint32_t)(U.je - U.jb) - chi;
+  if (U.slot_lo >= 1) atomicAdd(&A.hist[U.slot_lo * 64 + lane], clo);
+  if (U.slot_hi <= nb) atomicAdd(&A.hist[U.slot_hi * 64 + lane], chi);
+}
+
+// Weighted xi, binary64, two-slot unit (register sums).  exec = valid lanes.
+template <bool SHIFT>
+__device__ inline void loop_xi_f64_two_w(const PairParams &P, WaveArea A, const LanePt &L,
+                                         int lane, const Unit &U, const double *sE) {
+  const double Et = sE[U.slot_lo];
+  const int nb = P.nb;
+  const bool lo_real = U.slot_lo >= 1, hi_real = U.slot_hi <= nb;
+  const int wrapax[3] = {0, 0, 0};
+  uint32_t clo = 0, chi = 0;
+  double wlo = 0, whi = 0, rlo = 0, rhi = 0;
+  stream_f64(U.pos, U.jb, U.je, [&](int j, double ux, double uy, double uz, double uw) {
+    double dx, dy, dz;
+    ref_sep<SHIFT, false>(L.x, L.y, L.z, ux, uy, uz, U.S, wrapax, 0.0, 0.0, dx, dy, dz);
+    const double s64 = (dx * dx + dy * dy) + dz * dz;
+    const bool hi = s64 >= Et;
+    const bool counted = hi_real || !hi;
+    if (!wave_any(counted)) return;
+    const double wj = counted ? uw : 0.0;
+    const double wr = wj * sep_sqrt(s64);
+    if (hi_real) {
+      chi += hi ? 1u : 0u;
+      clo += hi ? 0u : 1u;
+      whi += hi ? wj : 0.0;
+      rhi += hi ? wr : 0.0;
+      wlo += hi ? 0.0 : wj;
+      rlo += hi ? 0.0 : wr;
+    } else {
+      clo += counted ? 1u : 0u;
+      wlo += wj;
+      rlo += wr;
+    }
+  });
+  if (lo_real) {
+    atomicAdd(&A.hist[U.slot_lo * 64 + lane], clo);
+    atomicAdd(&A.hw[U.slot_lo * kWStripe + (lane & (kWStripe - 1))], L.w * wlo);
+    atomicAdd(&A.hwr[U.slot_lo * kWStripe + (lane & (kWStripe - 1))], L.w * rlo);
+  }
+  if (hi_real) {
+    atomicAdd(&A.hist[U.slot_hi * 64 + lane], chi);
+    atomicAdd(&A.hw[U.slot_hi * kWStripe + (lane & (kWStripe - 1))], L.w * whi);
+    atomicAdd(&A.hwr[U.slot_hi * kWStripe + (lane & (kWStripe - 1))], L.w * rhi);
+  }
+}
+
 template <int MODE, bool OWN, bool SHIFT, bool WRAP, int W>
 __device__ inline void loop_f64(const PairParams &P, WaveArea A, const LanePt &L, int lane,
-                                int64_t jb, int64_t je, int64_t pbase, const double S[3],
-                                const int wrapax[3], double box, double half, const uint2 *tab64,
-                                const double *sE) {
-  sdouble *DP = (sdouble *)P.pos2;
+                                const Unit &U, const int wrapax[3], double box, double half,
+                                const uint2 *tab64, const double *sE) {
   const double EB = P.EB;
   const int lo = P.tab64_lo, hi = P.tab64_hi, sh = P.tab_shift;
   const int nb = P.nb, npi = P.npi;
-  for (int64_t j = jb; j < je; ++j) {
-    const double ux = DP[4 * j], uy = DP[4 * j + 1], uz = DP[4 * j + 2];
+  stream_f64(U.pos, U.jb, U.je, [&](int j, double ux, double uy, double uz, double uw) {
     double dx, dy, dz;
-    ref_sep<SHIFT, WRAP>(L.x, L.y, L.z, ux, uy, uz, S, wrapax, box, half, dx, dy, dz);
+    ref_sep<SHIFT, WRAP>(L.x, L.y, L.z, ux, uy, uz, U.S, wrapax, box, half, dx, dy, dz);
     const double rp2 = dx * dx + dy * dy;
     if (MODE == XI) {
       const double s64 = rp2 + dz * dz;
       bool inr = s64 < EB;
-      if (OWN) inr = inr && ((int)(j - pbase) > L.iloc);
-      if (!inr) continue;
-      const int slot = slot64(tab64, lo, hi, sh, sE, nb, s64);
-      atomicAdd(&A.hist[slot * 64 + lane], 1u);
-      if (W) {
-        const double ww = L.w * DP[4 * j + 3];
-        atomicAdd(&A.hw[slot * 64 + lane], ww);
-        atomicAdd(&A.hwr[slot * 64 + lane], ww * sqrt(s64));
+      if (OWN) inr = inr && (j > L.iloc);
+      if (!wave_any(inr)) return;
+      if (inr) {
+        const int slot = slot64(tab64, lo, hi, sh, sE, nb, s64);
+        atomicAdd(&A.hist[slot * 64 + lane], 1u);
+        if (W) {
+          const double ww = L.w * uw;
+          atomicAdd(&A.hw[slot * kWStripe + (lane & (kWStripe - 1))], ww);
+          atomicAdd(&A.hwr[slot * kWStripe + (lane & (kWStripe - 1))], ww * sep_sqrt(s64));
+        }
       }
     } else {
       const double pz64 = fabs(dz);
       bool inr = (rp2 < EB) && (pz64 < P.pimax);
-      if (OWN) inr = inr && ((int)(j - pbase) > L.iloc);
-      if (!inr) continue;
-      const int slot = slot64(tab64, lo, hi, sh, sE, nb, rp2);
-      const int l = exact_pibin(pz64, P.dpi, npi);
-      atomicAdd(&A.hist[slot * npi + l], 1u);
-      if (W) {
-        const double ww = L.w * DP[4 * j + 3];
-        atomicAdd(&A.hw[slot * npi + l], ww);
-        atomicAdd(&A.hwr[slot * npi + l], ww * sqrt(rp2));
+      if (OWN) inr = inr && (j > L.iloc);
+      if (!wave_any(inr)) return;
+      if (inr) {
+        const int slot = slot64(tab64, lo, hi, sh, sE, nb, rp2);
+        const int l = exact_pibin(pz64, P.dpi, npi);
+        atomicAdd(&A.hist[slot * npi + l], 1u);
+        if (W) {
+          const double ww = L.w * uw;
+          atomicAdd(&A.hw[slot * npi + l], ww);
+          atomicAdd(&A.hwr[slot * npi + l], ww * sep_sqrt(rp2));
+        }
       }
     }
-  }
+  });
 }
 
 // ------------------------------------------------------------------ kernel
@@ -373,7 +705,8 @@ __host__ __device__ inline LdsLayout lds_layout(int mode, int prec, int weighted
   const int NS = nb + 2;
   const size_t words = mode == XI ? (size_t)NS * 64 : (size_t)NS * npi;
   L.wave_hist = align16(words * 4);
-  L.wave_w = weighted ? words * 8 : 0;
+  // weight sums are shared by the wave (one row of slots), not lane-private
+  L.wave_w = weighted ? (mode == XI ? (size_t)NS * kWStripe : words) * 8 : 0;
   L.wave_bytes = L.wave_hist + 2 * L.wave_w;
   return L;
 }
@@ -399,9 +732,10 @@ __global__ __launch_bounds__(256) void k_pairs(PairParams P) {
   A.hwr = (double *)(wb + LY.wave_hist + LY.wave_w);
   const int NS = P.nslots;
   const int hwords = MODE == XI ? NS * 64 : NS * P.npi;
-  for (int t = lane; t < hwords; t += 64) {
-    A.hist[t] = 0u;
-    if (W) {
+  const int wwords = MODE == XI ? NS * kWStripe : hwords;
+  for (int t = lane; t < hwords; t += 64) A.hist[t] = 0u;
+  if (W) {
+    for (int t = lane; t < wwords; t += 64) {
       A.hw[t] = 0.0;
       A.hwr[t] = 0.0;
     }
@@ -462,7 +796,7 @@ __global__ __launch_bounds__(256) void k_pairs(PairParams P) {
 
     for (int base = 0; base < total; base += 64) {
       const int t = base + lane;
-      int keep = 0, pruned = 0, cell = 0, packed = 0;
+      int keep = 0, pruned = 0, cell = 0, packed = 0, slots = 0;
       if (t < total) {
         const int oz = t % nzr;
         const int rest = t / nzr;
@@ -501,7 +835,9 @@ __global__ __launch_bounds__(256) void k_pairs(PairParams P) {
             const double S0 = sx * box, S1 = sy * box, S2 = sz * box;
             const double tl[3] = {blx, bly, blz}, th[3] = {bhx, bhy, bhz};
             const double Sv[3] = {S0, S1, S2};
-            double m[3];
+            // The largest possible separation is bounded the same way, so
+            // every pair of the unit falls in [slot(lower), slot(upper)].
+            double m[3], M[3];
             for (int a = 0; a < 3; a++) {
               double gl = B.lo[a] - th[a];
               double gh = B.hi[a] - tl[a];
@@ -510,7 +846,11 @@ __global__ __launch_bounds__(256) void k_pairs(PairParams P) {
                 gh = gh + Sv[a];
               }
               m[a] = gl > 0.0 ? gl : (gh < 0.0 ? -gh : 0.0);
-              if (wrapax[a]) m[a] = 0.0;
+              M[a] = fmax(fabs(gl), fabs(gh));
+              if (wrapax[a]) {
+                m[a] = 0.0;
+                M[a] = half;
+              }
             }
             const double rp = m[0] * m[0] + m[1] * m[1];
             bool far;
@@ -519,6 +859,10 @@ __global__ __launch_bounds__(256) void k_pairs(PairParams P) {
             if (far) {
               ok = false;
               pruned = 1;
+            } else if (MODE == XI) {
+              const double slo = rp + m[2] * m[2];
+              const double shi = (M[0] * M[0] + M[1] * M[1]) + M[2] * M[2];
+              slots = exact_slot(sE, P.nb, slo) | (exact_slot(sE, P.nb, shi) << 8);
             }
           }
         }
@@ -536,68 +880,93 @@ __global__ __launch_bounds__(256) void k_pairs(PairParams P) {
         const int c2 = __builtin_amdgcn_readlane(cell, src);
         const int pk = __builtin_amdgcn_readlane(packed, src);
         const int kc = __builtin_amdgcn_readlane(keep, src);
+        const int sl = __builtin_amdgcn_readlane(slots, src);
         const int X = pk & 1023, Y = (pk >> 10) & 1023, Z = (pk >> 20) & 1023;
         const bool own = (pk >> 30) & 1;
         const int sxx = ((kc >> 1) & 3) - 1, syy = ((kc >> 3) & 3) - 1, szz = ((kc >> 5) & 3) - 1;
-        const double S[3] = {sxx * box, syy * box, szz * box};
         const bool shifted = (sxx | syy | szz) != 0;
         sint *CS = (sint *)P.cstart2;
-        const int64_t jb = pbase2 + CS[G2.sbase + c2];
-        const int64_t je = pbase2 + CS[G2.sbase + c2 + 1];
+        Unit U;
+        U.S[0] = sxx * box;
+        U.S[1] = syy * box;
+        U.S[2] = szz * box;
+        U.strm = P.strm2 + pbase2;
+        U.pos = P.pos2 + pbase2;
+        U.jb = CS[G2.sbase + c2];
+        U.je = CS[G2.sbase + c2 + 1];
+        U.slot_lo = sl & 255;
+        U.slot_hi = (sl >> 8) & 255;
+        const unsigned long long nj = (unsigned long long)(U.je - U.jb);
         st_cells++;
-        st_cand += (unsigned long long)nvalid * (unsigned long long)(je - jb);
-        since_flush += (unsigned long long)(je - jb);
+        since_flush += nj;
         if (since_flush > flush_limit) {
           flush_hist<MODE, W>(P, A, cur_mock, lane);
-          since_flush = (unsigned long long)(je - jb);
+          since_flush = nj;
         }
+        // all pairs of the unit in one bin: count them without separations
+        if (MODE == XI && !W && !own && !anywrap && U.slot_lo == U.slot_hi) {
+          if (U.slot_lo >= 1 && U.slot_lo <= P.nb && valid)
+            atomicAdd(&A.hist[U.slot_lo * 64 + lane], (uint32_t)nj);
+          continue;
+        }
+        st_cand += (unsigned long long)nvalid * nj;
+        const bool two = MODE == XI && !own && !anywrap && U.slot_hi == U.slot_lo + 1;
         if (PREC == F32R && !anywrap) {
-          const double ox = frame_origin(G2, 0, X) + S[0];
-          const double oy = frame_origin(G2, 1, Y) + S[1];
-          const double oz = frame_origin(G2, 2, Z) + S[2];
+          const double ox = frame_origin(G2, 0, X) + U.S[0];
+          const double oy = frame_origin(G2, 1, Y) + U.S[1];
+          const double oz = frame_origin(G2, 2, Z) + U.S[2];
           const float rxf = valid ? (float)(L.x - ox) : 1e18f;
           const float ryf = valid ? (float)(L.y - oy) : 1e18f;
           const float rzf = valid ? (float)(L.z - oz) : 1e18f;
           if (MODE == XI) {
             const float ra = __builtin_fmaf(rzf, rzf, __builtin_fmaf(ryf, ryf, rxf * rxf));
-#define CP_XI(O, SH)                                                                      \
-  loop_xi_f32<O, SH, W>(P, A, L, lane, rxf, ryf, rzf, ra, jb, je, pbase2, S, tab32, tab64, sE,  \
-                        nrechk)
-            if (own) { if (shifted) CP_XI(true, true); else CP_XI(true, false); }
-            else { if (shifted) CP_XI(false, true); else CP_XI(false, false); }
+            if (two) {
+              if (valid) {
+                if (W) {
+                  if (shifted) loop_xi_f32_two_w<true>(P, A, L, lane, rxf, ryf, rzf, ra, U, sE, nrechk);
+                  else loop_xi_f32_two_w<false>(P, A, L, lane, rxf, ryf, rzf, ra, U, sE, nrechk);
+                } else {
+                  if (shifted) loop_xi_f32_two<true>(P, A, L, lane, rxf, ryf, rzf, ra, U, sE, nrechk);
+                  else loop_xi_f32_two<false>(P, A, L, lane, rxf, ryf, rzf, ra, U, sE, nrechk);
+                }
+              }
+            } else {
+#define CP_XI(O, SH)                                                                     \
+  do {                                                                                   \
+    if (W) loop_xi_f32_w<O, SH>(P, A, L, lane, rxf, ryf, rzf, ra, U, tab32, sE, nrechk); \
+    else loop_xi_f32<O, SH>(P, A, L, lane, rxf, ryf, rzf, ra, U, tab32, sE, nrechk);     \
+  } while (0)
+              if (own) { if (shifted) CP_XI(true, true); else CP_XI(true, false); }
+              else { if (shifted) CP_XI(false, true); else CP_XI(false, false); }
 #undef CP_XI
+            }
           } else {
             const float ra = __builtin_fmaf(ryf, ryf, rxf * rxf);
-#define CP_WP(O, SH)                                                                      \
-  loop_wp_f32<O, SH, W>(P, A, L, lane, rxf, ryf, rzf, ra, jb, je, pbase2, S, tab32, tab64, sE,  \
-                        nrechk)
+#define CP_WP(O, SH) loop_wp_f32<O, SH, W>(P, A, L, lane, rxf, ryf, rzf, ra, U, tab32, sE, nrechk)
             if (own) { if (shifted) CP_WP(true, true); else CP_WP(true, false); }
             else { if (shifted) CP_WP(false, true); else CP_WP(false, false); }
 #undef CP_WP
           }
-        } else {
-          if (anywrap) {
-            if (own)
-              loop_f64<MODE, true, true, true, W>(P, A, L, lane, jb, je, pbase2, S, wrapax, box,
-                                                 half, tab64, sE);
-            else
-              loop_f64<MODE, false, true, true, W>(P, A, L, lane, jb, je, pbase2, S, wrapax, box,
-                                                  half, tab64, sE);
-          } else if (shifted) {
-            if (own)
-              loop_f64<MODE, true, true, false, W>(P, A, L, lane, jb, je, pbase2, S, wrapax, box,
-                                                  half, tab64, sE);
-            else
-              loop_f64<MODE, false, true, false, W>(P, A, L, lane, jb, je, pbase2, S, wrapax,
-                                                   box, half, tab64, sE);
-          } else {
-            if (own)
-              loop_f64<MODE, true, false, false, W>(P, A, L, lane, jb, je, pbase2, S, wrapax,
-                                                   box, half, tab64, sE);
-            else
-              loop_f64<MODE, false, false, false, W>(P, A, L, lane, jb, je, pbase2, S, wrapax,
-                                                    box, half, tab64, sE);
+        } else if (two) {
+          if (valid) {
+            if (W) {
+              if (shifted) loop_xi_f64_two_w<true>(P, A, L, lane, U, sE);
+              else loop_xi_f64_two_w<false>(P, A, L, lane, U, sE);
+            } else {
+              if (shifted) loop_xi_f64_two<true>(P, A, L, lane, U, sE);
+              else loop_xi_f64_two<false>(P, A, L, lane, U, sE);
+            }
           }
+        } else {
+#define CP_F64(O, SH, WR) loop_f64<MODE, O, SH, WR, W>(P, A, L, lane, U, wrapax, box, half, tab64, sE)
+          if (anywrap) {
+            if (own) CP_F64(true, true, true); else CP_F64(false, true, true);
+          } else if (shifted) {
+            if (own) CP_F64(true, true, false); else CP_F64(false, true, false);
+          } else {
+            if (own) CP_F64(true, false, false); else CP_F64(false, false, false);
+          }
+#undef CP_F64
         }
       }
     }
