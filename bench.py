@@ -92,7 +92,9 @@ def main():
     from paper_1911_08275_amd import native
     native.lib()  # fails loudly when the HIP library is missing
     refine = tuple(int(v) for v in args.refine.split(",")) if args.refine else None
-    rk = {} if refine is None else {"refine": refine}
+    # refine factors: given, or picked by the autotuner on first use (during
+    # warm-up, outside the timed steps)
+    rk = {"refine": refine if refine is not None else "auto"}
 
     # ---------------------------------------------------------- headline: C2
     c2 = synth.config2()

@@ -215,7 +215,10 @@ static Geometry choose_geometry(int mode, bool periodic, double box, const doubl
   const double reach[3] = {rmax, rmax, mode == XI ? rmax : pimax};
   int refine[3];
   for (int a = 0; a < 3; a++) {
-    int dflt = a < 2 ? 2 : 1;
+    // default: cells of R_max/2 on every axis (the paper's CPU default keeps
+    // z at R_max because its z-sorted late entry prunes along z; here finer
+    // z cells and the cell-level bounding-box test do that job)
+    int dflt = 2;
     refine[a] = refine_in && refine_in[a] > 0 ? refine_in[a] : dflt;
     if (refine[a] > 8) refine[a] = 8;
   }

@@ -1,0 +1,124 @@
+"""GPU parity at the full workload sizes (the benchmark's configurations).
+
+- xi, 10^6 clustered points, weighted (the headline workload): both
+  precisions against the oracle over the whole catalogue.
+- wp 2-D histogram, same generator: both precisions against the oracle.
+- float32 cross count D(10^6) x R(10^7), non-periodic: the oracle on a random
+  sample of D against all of R (the GPU counts the same sample against the
+  same R grid), plus properties of the full count that hold at any size
+  (binary32 == binary64; additivity over a split of D).
+- 256 mocks of 2*10^5..2*10^6 points in one plan: binary32 == binary64 for
+  every mock and every bin; the four smallest mocks against the oracle; every
+  mock equal to its single-call count for a sample of mocks.
+"""
+import time
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1911_08275_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def native():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1911_08275_amd import native
+    native.lib()
+    return native
+
+
+def test_headline_xi_weighted_full(native):
+    c = synth.config2()
+    _say("headline xi weighted: oracle")
+    t = time.time()
+    ref = oracle.xi(c["cat"], c["edges"], periodic=True, box=420.0)
+    _say(f"  oracle {time.time() - t:.1f}s")
+    d = native.to_device(c["cat"])
+    for prec in ("fp32", "fp64"):
+        g = native.countpairs_xi(d, c["edges"], precision=prec, periodic=True, boxsize=420.0,
+                                 need_ravg=True)
+        assert (g.npairs == ref.npairs).all(), (prec, g.npairs, ref.npairs)
+        np.testing.assert_allclose(g.wsum, ref.wsum, rtol=1e-12, atol=0)
+        np.testing.assert_allclose(g.ravg, ref.ravg, rtol=1e-12, atol=0)
+        _say(f"  {prec} ok, rechecks {g.stats['rechecks']}")
+
+
+def test_wp_full(native):
+    c = synth.config3()
+    _say("wp full: oracle")
+    t = time.time()
+    ref = oracle.wp(c["cat"], c["edges"], 40.0, 40, periodic=True, box=420.0)
+    _say(f"  oracle {time.time() - t:.1f}s")
+    d = native.to_device(c["cat"])
+    for prec in ("fp32", "fp64"):
+        g = native.countpairs_wp(d, c["edges"], 40.0, 40, precision=prec, periodic=True,
+                                 boxsize=420.0)
+        assert (g.npairs == ref.npairs).all(), prec
+
+
+def test_cross_full_sampled(native):
+    c = synth.config4()
+    rng = np.random.Generator(np.random.PCG64(77))
+    idx = np.sort(rng.choice(c["d"].n, 20_000, replace=False))
+    sub = c["d"].subset(idx)
+    dr = native.to_device(c["r"])
+    _say("cross sample: oracle")
+    t = time.time()
+    ref = oracle.xi(sub, c["edges"], periodic=False, other=c["r"])
+    _say(f"  oracle {time.time() - t:.1f}s")
+    for prec in ("fp32", "fp64"):
+        g = native.countpairs_cross(native.to_device(sub), dr, c["edges"], precision=prec,
+                                    periodic=False)
+        assert (g.npairs == ref.npairs).all(), prec
+    # full size: binary32 == binary64, and counts add up over a split of D
+    dd = native.to_device(c["d"])
+    f32 = native.countpairs_cross(dd, dr, c["edges"], precision="fp32", periodic=False)
+    f64 = native.countpairs_cross(dd, dr, c["edges"], precision="fp64", periodic=False)
+    assert (f32.npairs == f64.npairs).all()
+    half = c["d"].n // 2
+    a = c["d"].subset(np.arange(half))
+    b = c["d"].subset(np.arange(half, c["d"].n))
+    ga = native.countpairs_cross(native.to_device(a), dr, c["edges"], periodic=False)
+    gb = native.countpairs_cross(native.to_device(b), dr, c["edges"], periodic=False)
+    assert (ga.npairs + gb.npairs == f32.npairs).all()
+
+
+def test_batch_256_mocks(native):
+    import torch
+    specs = synth.mock_specs()
+    with ThreadPoolExecutor(8) as ex:
+        cats = list(ex.map(synth.mock, specs))
+    _say(f"batch: {len(cats)} mocks, {sum(c.n for c in cats)} points")
+    devs = [native.to_device(c) for c in cats]
+    xe = synth.log_edges(0.1, 25.0, 14)
+    res = {}
+    for prec in ("fp32", "fp64"):
+        plan = native.Plan(devs, xi_edges=xe, wp_edges=xe, pimax=40.0, npibins=40,
+                           precision=prec, periodic=True, boxsize=420.0)
+        plan.execute()
+        res[prec] = plan.results()
+        plan.close()
+        torch.cuda.synchronize()
+    assert (res["fp32"][0] == res["fp64"][0]).all()
+    assert (res["fp32"][1] == res["fp64"][1]).all()
+    xi, wp = res["fp32"]
+    order = np.argsort([c.n for c in cats])
+    for m in order[:4]:
+        _say(f"  mock {m} (n={cats[m].n}) vs oracle")
+        assert (xi[m] == oracle.xi(cats[m], xe, True, 420.0).npairs).all()
+        assert (wp[m] == oracle.wp(cats[m], xe, 40.0, 40, periodic=True, box=420.0).npairs).all()
+    for m in (int(order[-1]), int(order[len(order) // 2]), 0, 255):
+        s = native.countpairs_xi(devs[m], xe, periodic=True, boxsize=420.0)
+        assert (s.npairs == xi[m]).all()
+        s = native.countpairs_wp(devs[m], xe, 40.0, 40, periodic=True, boxsize=420.0)
+        assert (s.npairs == wp[m]).all()

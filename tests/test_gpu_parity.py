@@ -293,3 +293,22 @@ def test_plan_graph_replays(native):
     xi, _ = plan.results()
     _check(type("G", (), {"npairs": xi[1]})(), oracle.xi(new, xe, True, 420.0))
     plan.close()
+
+
+def test_autotuned_refine_same_counts(native, tmp_path, monkeypatch):
+    monkeypatch.setenv("CP_AUTOTUNE_CACHE", str(tmp_path / "at.json"))
+    cat = synth.clustered(40_000, 800, 1.5, 420.0, seed=12, weights=True)
+    edges = synth.log_edges(0.1, 25.0, 14)
+    d = native.to_device(cat)
+    ref = oracle.xi(cat, edges, periodic=True, box=420.0)
+    g = native.countpairs_xi(d, edges, periodic=True, boxsize=420.0, refine="auto",
+                             need_ravg=True)
+    _check(g, ref, weighted=True)
+    g = native.countpairs_wp(d, edges, 40.0, 40, periodic=True, boxsize=420.0, refine="auto")
+    _check(g, oracle.wp(cat, edges, 40.0, 40, periodic=True, box=420.0))
+    plan = native.Plan([d, native.to_device(synth.clustered(30_000, 600, 2.0, 420.0, seed=13))],
+                       xi_edges=edges, periodic=True, boxsize=420.0, refine="auto")
+    plan.execute()
+    xi, _ = plan.results()
+    assert (xi[0] == ref.npairs).all()
+    plan.close()
