@@ -647,11 +647,32 @@ static int run(const Call &c, uint64_t *npairs, double *wsum, double *ravg) {
   int *d_err0 = nullptr;
   if (!o.periodic) {
     // joint bounding box (Section 2.1: computed first) - needs a round trip
-    double *d_part = nullptr;
+    // scratch for the reduction: the head of the caller's workspace, or of
+    // the thread's cached arena (grown here if needed)
     const int nblk = 256;
-    HIPCHK(hipMallocAsync((void **)&d_part, sizeof(double) * (6 * nblk + 6) + 16, st));
+    const size_t pre = sizeof(double) * (6 * nblk + 6) + 64;
+    double *d_part = nullptr;
+    if (o.workspace) {
+      if (o.workspace_bytes < pre) return fail(CP_ERR_NOMEM, "workspace too small");
+      d_part = (double *)o.workspace;
+    } else {
+      if (g_arena.cap < pre) {
+        if (g_arena.base) {
+          HIPCHK(hipDeviceSynchronize());
+          (void)hipFree(g_arena.base);
+          g_arena.base = nullptr;
+          g_arena.cap = 0;
+        }
+        if (hipMalloc(&g_arena.base, 1 << 20) != hipSuccess) {
+          g_arena.base = nullptr;
+          return fail(CP_ERR_NOMEM, "hipMalloc of the scratch arena failed");
+        }
+        g_arena.cap = 1 << 20;
+      }
+      d_part = (double *)g_arena.base;
+    }
     d_err0 = (int *)(d_part + 6 * nblk + 6);
-    HIPCHK(hipMemsetAsync(d_err0, 0, sizeof(int), st));
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, d_err0, (int64_t)1, 0);
     PointsDev b = pd[1];
     if (autoc) b.n = 0;
     hipLaunchKernelGGL(k_bbox_partial, dim3(nblk), dim3(256), 0, st, pd[0], b, d_part, d_err0);
@@ -661,7 +682,6 @@ static int run(const Call &c, uint64_t *npairs, double *wsum, double *ravg) {
     HIPCHK(hipMemcpyAsync(bb, d_part + 6 * nblk, sizeof(bb), hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(&eflag, d_err0, sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
-    HIPCHK(hipFreeAsync(d_part, st));
     if ((rc = map_err_flags(eflag))) return rc;
     for (int a = 0; a < 3; a++) {
       lo[a] = bb[a];

@@ -164,7 +164,7 @@ def to_device(cat, device="cuda", weights: bool = True) -> DevicePoints:
 
 def options(precision: str = "fp32", periodic: bool = False, boxsize: float = 0.0,
             refine: Optional[Sequence[int]] = None, need_ravg: bool = False,
-            count_mode: str = "ordered", stream=None) -> cp_options:
+            count_mode: str = "ordered", stream=None, workspace=None) -> cp_options:
     o = cp_options()
     lib().cp_default_options(ctypes.byref(o))
     o.precision = {"fp32": CP_PREC_FP32_RECHECK, "fp64": CP_PREC_FP64}[precision]
@@ -175,6 +175,10 @@ def options(precision: str = "fp32", periodic: bool = False, boxsize: float = 0.
             o.refine[a] = int(refine[a])
     o.need_ravg = 1 if need_ravg else 0
     o.count_mode = {"ordered": CP_ORDERED, "unique": CP_UNIQUE}[count_mode]
+    if workspace is not None:
+        # a caller-owned device buffer (e.g. a torch uint8 tensor)
+        o.workspace = ctypes.c_void_p(workspace.data_ptr())
+        o.workspace_bytes = workspace.numel() * workspace.element_size()
     if stream is not None:
         o.stream = ctypes.c_void_p(int(getattr(stream, "cuda_stream", stream)))
     else:
@@ -380,3 +384,13 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def workspace_size(kind: str, n1: int, n2: int, edges, pimax: float = 0.0, npibins: int = 1,
+                   **opt) -> int:
+    """Bytes of device scratch a call needs at most (countpairs_workspace_size)."""
+    e = np.ascontiguousarray(edges, dtype=np.float64)
+    o = options(**opt)
+    k = {"xi": 0, "wp": 1, "cross": 2, "cross_wp": 3}[kind]
+    return int(lib().countpairs_workspace_size(k, int(n1), int(n2), _dp(e), e.size, float(pimax),
+                                                int(npibins), ctypes.byref(o)))

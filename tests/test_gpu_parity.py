@@ -312,3 +312,23 @@ def test_autotuned_refine_same_counts(native, tmp_path, monkeypatch):
     xi, _ = plan.results()
     assert (xi[0] == ref.npairs).all()
     plan.close()
+
+
+def test_caller_workspace(native):
+    import torch
+    cat = synth.clustered(30_000, 600, 1.5, 420.0, seed=14)
+    r = synth.uniform(40_000, 420.0, seed=15)
+    edges = synth.log_edges(0.1, 25.0, 14)
+    d, dr = native.to_device(cat), native.to_device(r)
+    nbytes = native.workspace_size("cross", cat.n, r.n, edges, periodic=False)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    g = native.countpairs_cross(d, dr, edges, periodic=False, workspace=ws)
+    _check(g, oracle.xi(cat, edges, periodic=False, other=r))
+    nbytes = native.workspace_size("xi", cat.n, 0, edges, periodic=True, boxsize=420.0)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    g = native.countpairs_xi(d, edges, periodic=True, boxsize=420.0, workspace=ws)
+    _check(g, oracle.xi(cat, edges, periodic=True, box=420.0))
+    small = torch.empty(4096, dtype=torch.uint8, device="cuda")
+    with pytest.raises(native.CountpairsError) as e:
+        native.countpairs_xi(d, edges, periodic=True, boxsize=420.0, workspace=small)
+    assert e.value.code == -4
