@@ -59,7 +59,7 @@ enum { CP_F64 = 0, CP_F32 = 1 };
 /* arithmetic of the distance evaluation */
 enum { CP_PREC_FP64 = 0, CP_PREC_FP32_RECHECK = 1 };
 /* auto-count convention: ordered pairs (each unordered pair counted twice,
- * Section 2.1 "double the total number of pairs found at the end") or unique
+ * as Section 2.1 obtains by doubling the unique-pair total) or unique
  * pairs (each unordered pair once) */
 enum { CP_ORDERED = 0, CP_UNIQUE = 1 };
 

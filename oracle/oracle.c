@@ -28,7 +28,8 @@
  *   - s = fl(fl(fl(dx*dx) + fl(dy*dy)) + fl(dz*dz)), left to right, unfused
  *     (the operation order of Code 3: rp^2 first, then + dz^2).
  *   - squared edges E_k = fl(e_k * e_k); bin k iff E_k <= s < E_{k+1}
- *     (half-open, as in Code 1's `dist < mindist || dist >= maxdist`).
+ *     (half-open: Code 1 skips a separation below the smallest edge or at or
+ *     above the largest one).
  *   - wp is kept as the 2-D histogram xi(rp, pi) of Section 1.1: pi bin l
  *     iff q_l <= pi < q_{l+1} with q_l = fl(l * fl(pi_max / npibins)) for
  *     0 < l < npibins, q_0 = 0 and q_npibins = pi_max.  Summing over l gives
@@ -38,8 +39,8 @@
  *     Neumaier-compensated so the oracle's own rounding stays far below the
  *     1e-12 relative tolerance used against the GPU.
  *   - auto-counts are returned as ORDERED pairs (each unordered pair twice),
- *     which is what "double the total number of pairs found at the end"
- *     (Section 2.1, "Reducing the number of cell pairs") yields.  The oracle
+ *     which is what counting unique pairs and doubling the total afterwards
+ *     (Section 2.1, "Reducing the number of cell pairs") gives.  The oracle
  *     visits ordered pairs directly and never doubles.
  *
  * Two enumerations of the same definition:
