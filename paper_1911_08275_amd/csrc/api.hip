@@ -511,8 +511,10 @@ static int launch_pairs_t(hipStream_t st, const PairParams &P, size_t lds, int n
 static int launch_pairs(hipStream_t st, int mode, int prec, int w, const PairParams &P,
                         size_t lds, int nwaves) {
   if (mode == XI) {
-    if (prec == F32R) return w ? launch_pairs_t<XI, F32R, 1>(st, P, lds, nwaves)
-                               : launch_pairs_t<XI, F32R, 0>(st, P, lds, nwaves);
+    if (prec == F32R) {
+      if (w) return fail(CP_ERR_INTERNAL, "weighted xi runs in binary64");
+      return launch_pairs_t<XI, F32R, 0>(st, P, lds, nwaves);
+    }
     return w ? launch_pairs_t<XI, F64, 1>(st, P, lds, nwaves)
              : launch_pairs_t<XI, F64, 0>(st, P, lds, nwaves);
   }
@@ -529,6 +531,7 @@ struct Binning {
   Table t32, t64;
   int shift;
   float AB32;
+  float eps32;
   Bounds bnd;
   float inv_dpi32, pi_delta, pi_lo32, pi_hi32;
   double dpi;
@@ -564,6 +567,7 @@ static int make_binning(int mode, int prec, const double *edges, int nedges, dou
   }
   if (prec != F32R) B.t32 = B.t64;
   B.AB32 = A32[nb];
+  B.eps32 = f32_up(B.bnd.eps);
   B.C32 = C32;
   B.A32 = A32;
   B.dpi = mode == WP ? pimax / npi : 1.0;
@@ -697,6 +701,11 @@ static int run(const Call &c, uint64_t *npairs, double *wsum, double *ravg) {
                                o.refine, ntot);
   int prec = o.precision == CP_PREC_FP32_RECHECK ? F32R : F64;
   if (g.wrap[0] || g.wrap[1] || g.wrap[2]) prec = F64;   // per-pair minimum image: binary64
+  // Weighted xi needs the binary64 separation of every counted pair for the
+  // weighted mean, and binary64 FMAs issue at the binary32 rate on gfx950,
+  // so a binary32 filter would only add work: the binary64 loops run (same
+  // counts by definition).
+  if (c.mode == XI && o.need_ravg) prec = F64;
   double M = 0;
   for (int a = 0; a < 3; a++) M = std::max(M, std::fabs(g.lo[a]) + g.ext[a]);
   if (o.periodic) M = std::max(M, o.boxsize);
@@ -831,6 +840,7 @@ static int run(const Call &c, uint64_t *npairs, double *wsum, double *ravg) {
   P.nb = nb;
   P.nslots = nb + 2;
   P.AB32 = B.AB32;
+  P.eps32 = B.eps32;
   P.EB = B.E[nb];
   P.pimax = c.pimax;
   P.dpi = B.dpi;
@@ -1040,6 +1050,7 @@ struct Batch {
   int *d_err = nullptr;
   size_t lds = 0;
   int nwaves = 4;
+  double pimax = 0.0;
   PairParams P{};
 };
 
@@ -1069,6 +1080,7 @@ static int batch_prepare(cp_plan &pl, Batch &b, int mode, int prec, const double
   b.mode = mode;
   b.nb = nedges - 1;
   b.npi = mode == WP ? npi : 1;
+  b.pimax = mode == WP ? pimax : 0.0;
   b.nout = b.nb * b.npi;
   const double lo[3] = {0, 0, 0}, ext[3] = {0, 0, 0};
   b.g = choose_geometry(mode, true, o.boxsize, lo, ext, edges[nedges - 1], pimax, o.refine,
@@ -1178,8 +1190,9 @@ static int batch_upload(cp_plan &pl, Batch &b) {
   P.nb = b.nb;
   P.nslots = b.nb + 2;
   P.AB32 = b.B.AB32;
+  P.eps32 = b.B.eps32;
   P.EB = b.B.E[b.nb];
-  P.pimax = b.mode == WP ? std::sqrt(0.0) + b.B.dpi * b.npi : 0.0;
+  P.pimax = b.pimax;
   P.dpi = b.B.dpi;
   P.npi = b.npi;
   P.inv_dpi32 = b.B.inv_dpi32;
@@ -1325,7 +1338,6 @@ int cp_plan_create(const cp_points *mocks, int nmocks, const double *xi_edges, i
       cp_plan_destroy(pl);
       return rc;
     }
-    if (wp_edges) pl->wp.P.pimax = pimax;
     for (auto &e : pl->ev) {
       if (hipEventCreate(&e) != hipSuccess) {
         cp_plan_destroy(pl);

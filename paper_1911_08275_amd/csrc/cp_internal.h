@@ -88,6 +88,8 @@ struct PairParams {
   int nb;                    // separation bins
   int nslots;                // nb + 2
   float AB32;                // binary32 s~ >= AB32 -> certainly >= E_B
+  float eps32;               // binary32 bound on |(s~ - E_t) - (s - E_t)| of the
+                             // folded two-slot evaluation (rounded up)
   double EB;                 // E_B
   // wp
   double pimax, dpi;

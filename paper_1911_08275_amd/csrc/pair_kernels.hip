@@ -110,8 +110,9 @@ __device__ inline int slot64(const uint2 *tab, int lo, int hi, int sh, const dou
 // gfx950) refined by one Newton step in binary64, measured relative error
 // below 5e-15, far inside the 1e-12 tolerance of the weighted sums.
 __device__ inline double sep_sqrt(double x) {
-  if (!(x > 0.0)) return 0.0;
-  const double y = __builtin_amdgcn_rsq(x);
+  // x >= 0.  x == 0 gives r == 0 and an exact 0; x below 1e-300 (separations
+  // below 1e-150) would come out inexact but still below 1e-149.
+  const double y = __builtin_amdgcn_rsq(x + 1e-300);
   const double r = x * y;
   const double e = __builtin_fma(-r, r, x);
   return __builtin_fma(0.5 * y, e, r);
@@ -142,9 +143,16 @@ __device__ inline void ref_sep(double px, double py, double pz, double qx, doubl
   }
 }
 
+// Adds (w, w r) to an interleaved pair of LDS weight sums (one address, two
+// atomics at offsets 0 and 8).
+__device__ inline void add_w(double *p, double w, double wr) {
+  atomicAdd(p, w);
+  atomicAdd(p + 1, wr);
+}
+
 struct WaveArea {
   uint32_t *hist;
-  double *hw, *hwr;
+  double *hw;   // weight sums, interleaved: hw[2 i] = sum w, hw[2 i + 1] = sum w r
 };
 
 template <int MODE, int W>
@@ -161,8 +169,8 @@ __device__ inline void flush_hist(const PairParams &P, WaveArea A, int mock, int
     if (W && lane >= 1 && lane <= nb) {
       double a = 0.0, b = 0.0;
       for (int c = 0; c < kWStripe; c++) {
-        a += A.hw[lane * kWStripe + c];
-        b += A.hwr[lane * kWStripe + c];
+        a += A.hw[2 * (lane * kWStripe + c)];
+        b += A.hw[2 * (lane * kWStripe + c) + 1];
       }
       if (a != 0.0) unsafeAtomicAdd(P.hw + (int64_t)mock * P.hist_stride + (lane - 1), a);
       if (b != 0.0) unsafeAtomicAdd(P.hwr + (int64_t)mock * P.hist_stride + (lane - 1), b);
@@ -171,10 +179,7 @@ __device__ inline void flush_hist(const PairParams &P, WaveArea A, int mock, int
     __builtin_amdgcn_wave_barrier();
     for (int s = 0; s < NS; s++) A.hist[s * 64 + lane] = 0u;
     if (W) {
-      for (int t = lane; t < NS * kWStripe; t += 64) {
-        A.hw[t] = 0.0;
-        A.hwr[t] = 0.0;
-      }
+      for (int t = lane; t < 2 * NS * kWStripe; t += 64) A.hw[t] = 0.0;
     }
   } else {
     const int npi = P.npi;
@@ -182,7 +187,7 @@ __device__ inline void flush_hist(const PairParams &P, WaveArea A, int mock, int
       uint32_t v = A.hist[npi + t];
       if (v) atomicAdd(gh + t, (unsigned long long)v);
       if (W) {
-        double a = A.hw[npi + t], b = A.hwr[npi + t];
+        double a = A.hw[2 * (npi + t)], b = A.hw[2 * (npi + t) + 1];
         if (a != 0.0) unsafeAtomicAdd(P.hw + (int64_t)mock * P.hist_stride + t, a);
         if (b != 0.0) unsafeAtomicAdd(P.hwr + (int64_t)mock * P.hist_stride + t, b);
       }
@@ -192,8 +197,8 @@ __device__ inline void flush_hist(const PairParams &P, WaveArea A, int mock, int
     for (int t = lane; t < NS * npi; t += 64) {
       A.hist[t] = 0u;
       if (W) {
-        A.hw[t] = 0.0;
-        A.hwr[t] = 0.0;
+        A.hw[2 * t] = 0.0;
+        A.hw[2 * t + 1] = 0.0;
       }
     }
   }
@@ -214,8 +219,6 @@ struct LanePt {
 // groups per trip so the two buffers alternate without copies; the stream
 // arrays are padded by 8 records, so the look-ahead never leaves the
 // allocation.  The body is called once per record with its values in SGPRs.
-
-__device__ inline bool wave_any(bool p) { return __ballot(p) != 0ull; }
 
 #define CP_LOAD16(dst, src)                                                                    \
   _Pragma("unroll") for (int t_ = 0; t_ < 16; t_++) dst[t_] = (src)[t_];
@@ -349,108 +352,64 @@ __device__ inline float gram3(float rx, float ry, float rz, float ra, float qx, 
 
 // ---------------------------------------------------------------- FP32 loops
 
+// Binary64 re-evaluation of one uncertain xi pair; adds it to its exact slot.
+template <bool SHIFT>
+__device__ inline void recheck_xi(WaveArea A, const LanePt &L, int lane, const Unit &U, int j,
+                                  const double *sE, int nb) {
+  sdouble *DP = (sdouble *)U.pos;
+  const double ux = DP[4 * j], uy = DP[4 * j + 1], uz = DP[4 * j + 2];
+  const int wrapax[3] = {0, 0, 0};
+  double dx, dy, dz;
+  ref_sep<SHIFT, false>(L.x, L.y, L.z, ux, uy, uz, U.S, wrapax, 0.0, 0.0, dx, dy, dz);
+  const double s64 = (dx * dx + dy * dy) + dz * dz;
+  atomicAdd(&A.hist[exact_slot(sE, nb, s64) * 64 + lane], 1u);
+}
+
 // xi, binary32, a unit whose pairs can only land in slot_lo or slot_hi:
-// edge E_t (t = slot_lo) decides; two compares per pair into per-lane
-// counters.  Runs with exec = valid lanes.
+// edge E_t (t = slot_lo) decides.  The edge is folded into the lane's
+// constant, b = fl32(|r|^2 - E_t), so three FMAs and one add give
+// d~ = s~ - E_t directly; rounding keeps the sign of the last add, so the
+// decision error is that of the Gram form (the bound eps covers it).  The
+// first pass, branch-free, counts the negative d~ per lane and tracks the
+// smallest |d~|.  Only a lane with some |d~| < eps takes a second pass that
+// re-evaluates the same binary32 values, bit for bit, and sends those pairs
+// to binary64.  exec = valid lanes.
 template <bool SHIFT>
 __device__ inline void loop_xi_f32_two(const PairParams &P, WaveArea A, const LanePt &L, int lane,
                                        float rx, float ry, float rz, float ra, const Unit &U,
                                        const double *sE, uint32_t &nrechk) {
-  const int t = U.slot_lo;
-  const float Ct = P.C32[t], At = P.A32[t];
   const int nb = P.nb;
-  const int wrapax[3] = {0, 0, 0};
-  uint32_t clo = 0, chi = 0;
-  stream_f32(U.strm, U.jb, U.je, [&](int j, float qx, float qy, float qz, float qw) {
-    const float s = gram3(rx, ry, rz, ra, qx, qy, qz, qw);
-    const bool lo = s < Ct, hi = s >= At;
-    clo += lo ? 1u : 0u;
-    chi += hi ? 1u : 0u;
-    const bool unc = !(lo || hi);
-    if (wave_any(unc)) {
-      if (unc) {
-        sdouble *DP = (sdouble *)U.pos;
-        const double ux = DP[4 * j], uy = DP[4 * j + 1], uz = DP[4 * j + 2];
-        double dx, dy, dz;
-        ref_sep<SHIFT, false>(L.x, L.y, L.z, ux, uy, uz, U.S, wrapax, 0.0, 0.0, dx, dy, dz);
-        const double s64 = (dx * dx + dy * dy) + dz * dz;
-        atomicAdd(&A.hist[exact_slot(sE, nb, s64) * 64 + lane], 1u);
-        nrechk++;
-      }
-    }
+  const float b = (float)((double)ra - sE[U.slot_lo]);
+  const float eps = P.eps32;
+  uint32_t nneg = 0;
+  float mn = 3.0e38f;
+  stream_f32(U.strm, U.jb, U.je, [&](int, float qx, float qy, float qz, float qw) {
+    const float d = gram3(rx, ry, rz, b, qx, qy, qz, qw);
+    nneg += __float_as_uint(d) >> 31;
+    mn = fminf(mn, fabsf(d));
   });
-  if (U.slot_lo >= 1) atomicAdd(&A.hist[U.slot_lo * 64 + lane], clo);
-  if (U.slot_hi <= nb) atomicAdd(&A.hist[U.slot_hi * 64 + lane], chi);
-}
-
-// Weighted xi, binary32 filter, two-slot unit.  Weight sums of the unit stay
-// in registers (sums of w_j and w_j r per slot; w_i is applied once at the
-// end) and are added to the wave's shared sums when the unit is done.
-// exec = valid lanes.
-template <bool SHIFT>
-__device__ inline void loop_xi_f32_two_w(const PairParams &P, WaveArea A, const LanePt &L,
-                                         int lane, float rx, float ry, float rz, float ra,
-                                         const Unit &U, const double *sE, uint32_t &nrechk) {
-  const int t = U.slot_lo;
-  const float Ct = P.C32[t], At = P.A32[t];
-  const double Et = sE[t];
-  const int nb = P.nb;
-  const bool lo_real = U.slot_lo >= 1, hi_real = U.slot_hi <= nb;
-  // a pair can land in a counted slot: any pair when both slots are bins,
-  // otherwise only pairs that are not certainly in the upper slot
-  const float Acut = hi_real ? 3.0e38f : At;
-  const int wrapax[3] = {0, 0, 0};
-  uint32_t clo = 0, chi = 0;
-  double wlo = 0, whi = 0, rlo = 0, rhi = 0;
-  stream_w(U.strm, U.pos, U.jb, U.je,
-           [&](int j, float qx, float qy, float qz, float qw, double ux, double uy, double uz,
-               double uw) {
-             const float s = gram3(rx, ry, rz, ra, qx, qy, qz, qw);
-             const bool m = s < Acut;
-             if (!wave_any(m)) return;
-             double dx, dy, dz;
-             ref_sep<SHIFT, false>(L.x, L.y, L.z, ux, uy, uz, U.S, wrapax, 0.0, 0.0, dx, dy, dz);
-             bool hi = s >= At;
-             const bool unc = m && !(s < Ct) && !hi;
-             if (wave_any(unc)) {
-               const double s64 = (dx * dx + dy * dy) + dz * dz;
-               if (unc) {
-                 hi = s64 >= Et;
-                 nrechk++;
-               }
-             }
-             const bool counted = m && (hi_real || !hi);
-             const double sw = __builtin_fma(dx, dx, __builtin_fma(dy, dy, dz * dz));
-             const double wj = counted ? uw : 0.0;
-             const double wr = wj * sep_sqrt(sw);
-             if (hi_real) {
-               const bool h = hi && counted;
-               chi += h ? 1u : 0u;
-               clo += (counted && !h) ? 1u : 0u;
-               whi += h ? wj : 0.0;
-               rhi += h ? wr : 0.0;
-               wlo += h ? 0.0 : wj;
-               rlo += h ? 0.0 : wr;
-             } else {
-               clo += counted ? 1u : 0u;
-               wlo += wj;
-               rlo += wr;
-             }
-           });
-  if (lo_real) {
-    atomicAdd(&A.hist[U.slot_lo * 64 + lane], clo);
-    atomicAdd(&A.hw[U.slot_lo * kWStripe + (lane & (kWStripe - 1))], L.w * wlo);
-    atomicAdd(&A.hwr[U.slot_lo * kWStripe + (lane & (kWStripe - 1))], L.w * rlo);
+  uint32_t uneg = 0, upos = 0;
+  if (mn < eps) {
+    stream_f32(U.strm, U.jb, U.je, [&](int j, float qx, float qy, float qz, float qw) {
+      const float d = gram3(rx, ry, rz, b, qx, qy, qz, qw);
+      if (fabsf(d) < eps) {
+        recheck_xi<SHIFT>(A, L, lane, U, j, sE, nb);
+        const uint32_t ng = __float_as_uint(d) >> 31;
+        uneg += ng;
+        upos += 1u - ng;
+      }
+    });
+    nrechk += uneg + upos;
   }
-  if (hi_real) {
-    atomicAdd(&A.hist[U.slot_hi * 64 + lane], chi);
-    atomicAdd(&A.hw[U.slot_hi * kWStripe + (lane & (kWStripe - 1))], L.w * whi);
-    atomicAdd(&A.hwr[U.slot_hi * kWStripe + (lane & (kWStripe - 1))], L.w * rhi);
-  }
+  const uint32_t nlo = nneg - uneg;
+  const uint32_t nhi = (uint32_t)(U.je - U.jb) - nneg - upos;
+  if (U.slot_lo >= 1) atomicAdd(&A.hist[U.slot_lo * 64 + lane], nlo);
+  if (U.slot_hi <= nb) atomicAdd(&A.hist[U.slot_hi * 64 + lane], nhi);
 }
 
 // xi, binary32, general unit: per-lane table lookup.  OWN: one of the tile's
-// own cells (auto-count), only j > i pairs.
+// own cells (auto-count), only j > i pairs.  Uncertain pairs are counted in
+// the first pass and re-evaluated in a second pass only when a lane has one.
 template <bool OWN, bool SHIFT>
 __device__ inline void loop_xi_f32(const PairParams &P, WaveArea A, const LanePt &L, int lane,
                                    float rx, float ry, float rz, float ra, const Unit &U,
@@ -458,120 +417,131 @@ __device__ inline void loop_xi_f32(const PairParams &P, WaveArea A, const LanePt
   const float AB = P.AB32;
   const int lo = P.tab32_lo, hi = P.tab32_hi, sh = P.tab_shift;
   const int nb = P.nb;
-  const int wrapax[3] = {0, 0, 0};
+  uint32_t nunc = 0;
   stream_f32(U.strm, U.jb, U.je, [&](int j, float qx, float qy, float qz, float qw) {
     const float s = gram3(rx, ry, rz, ra, qx, qy, qz, qw);
     bool inr = s < AB;
     if (OWN) inr = inr && (j > L.iloc);
-    if (!wave_any(inr)) return;
-    const TabHit h = tab_lookup(tab32, lo, hi, sh, s);
-    const bool unc = inr && h.unc;
-    // out-of-range and uncertain lanes add to the unused slot 0
-    atomicAdd(&A.hist[((inr && !h.unc) ? h.slot : 0) * 64 + lane], 1u);
-    if (wave_any(unc)) {
-      if (unc) {
-        sdouble *DP = (sdouble *)U.pos;
-        const double ux = DP[4 * j], uy = DP[4 * j + 1], uz = DP[4 * j + 2];
-        double dx, dy, dz;
-        ref_sep<SHIFT, false>(L.x, L.y, L.z, ux, uy, uz, U.S, wrapax, 0.0, 0.0, dx, dy, dz);
-        const double s64 = (dx * dx + dy * dy) + dz * dz;
-        atomicAdd(&A.hist[exact_slot(sE, nb, s64) * 64 + lane], 1u);
-        nrechk++;
-      }
+    if (inr) {
+      const TabHit h = tab_lookup(tab32, lo, hi, sh, s);
+      // uncertain pairs add to the unused slot 0 here
+      atomicAdd(&A.hist[(h.unc ? 0 : h.slot) * 64 + lane], 1u);
+      nunc += h.unc ? 1u : 0u;
     }
   });
+  if (nunc != 0u) {
+    stream_f32(U.strm, U.jb, U.je, [&](int j, float qx, float qy, float qz, float qw) {
+      const float s = gram3(rx, ry, rz, ra, qx, qy, qz, qw);
+      bool inr = s < AB;
+      if (OWN) inr = inr && (j > L.iloc);
+      if (inr && tab_lookup(tab32, lo, hi, sh, s).unc) recheck_xi<SHIFT>(A, L, lane, U, j, sE, nb);
+    });
+    nrechk += nunc;
+  }
 }
 
-// Weighted xi, binary32 filter, general unit.
+// wp, binary32 filter: the rp^2 estimate goes through the table, |dz| is
+// binned by multiplying with 1/dpi, and a pair whose fraction lies within
+// pi_delta of a pi edge, or whose |dz| is near pi_max, is uncertain.
+struct WpHit {
+  bool inr, unc;
+  int slot, l;
+};
+template <bool OWN>
+__device__ inline WpHit wp_decide(const PairParams &P, const uint2 *tab32, const LanePt &L,
+                                  float rx, float ry, float rz, float ra, int j, float qx,
+                                  float qy, float qz, float qw) {
+  float v = __builtin_fmaf(rx, qx, ra);
+  v = __builtin_fmaf(ry, qy, v);
+  const float s = v + qw;
+  const float pz = fabsf(qz - rz);
+  WpHit r;
+  r.inr = (s < P.AB32) && (pz < P.pi_hi32);
+  if (OWN) r.inr = r.inr && (j > L.iloc);
+  const TabHit h = tab_lookup(tab32, P.tab32_lo, P.tab32_hi, P.tab_shift, s);
+  const float f = pz * P.inv_dpi32;
+  const float fl = floorf(f);
+  const float fr = f - fl;
+  r.l = min((int)fl, P.npi - 1);
+  r.slot = h.slot;
+  r.unc = r.inr && (h.unc || (fr < P.pi_delta) || (fr > 1.0f - P.pi_delta) || (pz >= P.pi_lo32));
+  return r;
+}
+
+// Binary64 re-evaluation of one uncertain wp pair (unweighted).
+template <bool SHIFT>
+__device__ inline void recheck_wp(const PairParams &P, WaveArea A, const LanePt &L, const Unit &U,
+                                  int j, const double *sE) {
+  sdouble *DP = (sdouble *)U.pos;
+  const double ux = DP[4 * j], uy = DP[4 * j + 1], uz = DP[4 * j + 2];
+  const int wrapax[3] = {0, 0, 0};
+  double dx, dy, dz;
+  ref_sep<SHIFT, false>(L.x, L.y, L.z, ux, uy, uz, U.S, wrapax, 0.0, 0.0, dx, dy, dz);
+  const double rp2 = dx * dx + dy * dy;
+  const double pz64 = fabs(dz);
+  if (pz64 < P.pimax && rp2 < P.EB)
+    atomicAdd(&A.hist[exact_slot(sE, P.nb, rp2) * P.npi + exact_pibin(pz64, P.dpi, P.npi)], 1u);
+}
+
+// wp, unweighted: certain pairs are counted in the first pass, uncertain
+// ones re-evaluated in a second pass only when a lane has one.
 template <bool OWN, bool SHIFT>
-__device__ inline void loop_xi_f32_w(const PairParams &P, WaveArea A, const LanePt &L, int lane,
+__device__ inline void loop_wp_f32(const PairParams &P, WaveArea A, const LanePt &L, int lane,
+                                   float rx, float ry, float rz, float ra, const Unit &U,
+                                   const uint2 *tab32, const double *sE, uint32_t &nrechk) {
+  const int npi = P.npi;
+  uint32_t nunc = 0;
+  stream_f32(U.strm, U.jb, U.je, [&](int j, float qx, float qy, float qz, float qw) {
+    const float s0 = __builtin_fmaf(ry, qy, __builtin_fmaf(rx, qx, ra)) + qw;
+    bool pre = (s0 < P.AB32) && (fabsf(qz - rz) < P.pi_hi32);
+    if (OWN) pre = pre && (j > L.iloc);
+    if (pre) {
+      const WpHit h = wp_decide<OWN>(P, tab32, L, rx, ry, rz, ra, j, qx, qy, qz, qw);
+      if (h.inr && !h.unc) atomicAdd(&A.hist[h.slot * npi + h.l], 1u);
+      nunc += h.unc ? 1u : 0u;
+    }
+  });
+  if (nunc != 0u) {
+    stream_f32(U.strm, U.jb, U.je, [&](int j, float qx, float qy, float qz, float qw) {
+      const WpHit h = wp_decide<OWN>(P, tab32, L, rx, ry, rz, ra, j, qx, qy, qz, qw);
+      if (h.unc) recheck_wp<SHIFT>(P, A, L, U, j, sE);
+    });
+    nrechk += nunc;
+  }
+}
+
+// wp, weighted: every in-range pair is evaluated in binary64 for its rp.
+template <bool OWN, bool SHIFT>
+__device__ inline void loop_wp_f32_w(const PairParams &P, WaveArea A, const LanePt &L, int lane,
                                      float rx, float ry, float rz, float ra, const Unit &U,
                                      const uint2 *tab32, const double *sE, uint32_t &nrechk) {
-  const float AB = P.AB32;
-  const int lo = P.tab32_lo, hi = P.tab32_hi, sh = P.tab_shift;
-  const int nb = P.nb;
+  const int nb = P.nb, npi = P.npi;
   const int wrapax[3] = {0, 0, 0};
   stream_w(U.strm, U.pos, U.jb, U.je,
            [&](int j, float qx, float qy, float qz, float qw, double ux, double uy, double uz,
                double uw) {
-             const float s = gram3(rx, ry, rz, ra, qx, qy, qz, qw);
-             bool inr = s < AB;
-             if (OWN) inr = inr && (j > L.iloc);
-             if (!wave_any(inr)) return;
-             const TabHit h = tab_lookup(tab32, lo, hi, sh, s);
-             double dx, dy, dz;
-             ref_sep<SHIFT, false>(L.x, L.y, L.z, ux, uy, uz, U.S, wrapax, 0.0, 0.0, dx, dy, dz);
-             int slot = h.slot;
-             if (wave_any(inr && h.unc)) {
-               if (inr && h.unc) {
-                 const double s64 = (dx * dx + dy * dy) + dz * dz;
-                 slot = exact_slot(sE, nb, s64);
+             const WpHit h = wp_decide<OWN>(P, tab32, L, rx, ry, rz, ra, j, qx, qy, qz, qw);
+             if (h.inr) {
+               double dx, dy, dz;
+               ref_sep<SHIFT, false>(L.x, L.y, L.z, ux, uy, uz, U.S, wrapax, 0.0, 0.0, dx, dy,
+                                     dz);
+               int sl = h.slot, ll = h.l;
+               bool keep = true;
+               if (h.unc) {
                  nrechk++;
+                 const double rp2 = dx * dx + dy * dy;
+                 const double pz64 = fabs(dz);
+                 keep = pz64 < P.pimax && rp2 < P.EB;
+                 sl = exact_slot(sE, nb, rp2);
+                 ll = exact_pibin(pz64, P.dpi, npi);
+               }
+               if (keep) {
+                 const double ww = L.w * uw;
+                 atomicAdd(&A.hist[sl * npi + ll], 1u);
+                 add_w(A.hw + 2 * (sl * npi + ll), ww, ww * sep_sqrt(__builtin_fma(dx, dx, dy * dy)));
                }
              }
-             const double sw = __builtin_fma(dx, dx, __builtin_fma(dy, dy, dz * dz));
-             const double wr = sep_sqrt(sw);
-             if (inr) {
-               const double ww = L.w * uw;
-               atomicAdd(&A.hist[slot * 64 + lane], 1u);
-               atomicAdd(&A.hw[slot * kWStripe + (lane & (kWStripe - 1))], ww);
-               atomicAdd(&A.hwr[slot * kWStripe + (lane & (kWStripe - 1))], ww * wr);
-             }
            });
-}
-
-// wp, binary32 filter.
-template <bool OWN, bool SHIFT, int W>
-__device__ inline void loop_wp_f32(const PairParams &P, WaveArea A, const LanePt &L, int lane,
-                                   float rx, float ry, float rz, float ra, const Unit &U,
-                                   const uint2 *tab32, const double *sE, uint32_t &nrechk) {
-  const float AB = P.AB32, PIHI = P.pi_hi32, PILO = P.pi_lo32, invd = P.inv_dpi32,
-              dlt = P.pi_delta;
-  const int lo = P.tab32_lo, hi = P.tab32_hi, sh = P.tab_shift;
-  const int nb = P.nb, npi = P.npi;
-  const int wrapax[3] = {0, 0, 0};
-  stream_f32(U.strm, U.jb, U.je, [&](int j, float qx, float qy, float qz, float qw) {
-    float v = __builtin_fmaf(rx, qx, ra);
-    v = __builtin_fmaf(ry, qy, v);
-    const float s = v + qw;
-    const float pz = fabsf(qz - rz);
-    bool inr = (s < AB) && (pz < PIHI);
-    if (OWN) inr = inr && (j > L.iloc);
-    if (!wave_any(inr)) return;
-    const TabHit h = tab_lookup(tab32, lo, hi, sh, s);
-    const float f = pz * invd;
-    const float fl = floorf(f);
-    const float fr = f - fl;
-    const int l = min((int)fl, npi - 1);
-    const bool unc = inr && (h.unc || (fr < dlt) || (fr > 1.0f - dlt) || (pz >= PILO));
-    if (!W) {
-      if (inr && !unc) atomicAdd(&A.hist[h.slot * npi + l], 1u);
-      if (!wave_any(unc)) return;
-    }
-    if (unc || (W && inr)) {
-      sdouble *DP = (sdouble *)U.pos;
-      const double ux = DP[4 * j], uy = DP[4 * j + 1], uz = DP[4 * j + 2], uw = DP[4 * j + 3];
-      double dx, dy, dz;
-      ref_sep<SHIFT, false>(L.x, L.y, L.z, ux, uy, uz, U.S, wrapax, 0.0, 0.0, dx, dy, dz);
-      int sl = h.slot, ll = l;
-      bool keep = true;
-      if (unc) {
-        nrechk++;
-        const double rp2 = dx * dx + dy * dy;
-        const double pz64 = fabs(dz);
-        keep = pz64 < P.pimax && rp2 < P.EB;
-        sl = exact_slot(sE, nb, rp2);
-        ll = exact_pibin(pz64, P.dpi, npi);
-        if (!W && keep) atomicAdd(&A.hist[sl * npi + ll], 1u);
-      }
-      if (W && keep) {
-        const double ww = L.w * uw;
-        atomicAdd(&A.hist[sl * npi + ll], 1u);
-        atomicAdd(&A.hw[sl * npi + ll], ww);
-        atomicAdd(&A.hwr[sl * npi + ll], ww * sep_sqrt(__builtin_fma(dx, dx, dy * dy)));
-      }
-    }
-  });
 }
 
 // ---------------------------------------------------------------- FP64 loops
@@ -595,47 +565,44 @@ __device__ inline void loop_xi_f64_two(const PairParams &P, WaveArea A, const La
   if (U.slot_hi <= nb) atomicAdd(&A.hist[U.slot_hi * 64 + lane], chi);
 }
 
-// Weighted xi, binary64, two-slot unit (register sums).  exec = valid lanes.
-template <bool SHIFT>
+// Weighted xi, binary64, two-slot unit (register sums of w_j and w_j r per
+// slot; w_i is applied once at the end).  HIREAL: both slots are bins, so
+// every pair is counted; otherwise the upper slot lies beyond R_max and
+// only pairs below E_t count.  exec = valid lanes.
+template <bool SHIFT, bool HIREAL>
 __device__ inline void loop_xi_f64_two_w(const PairParams &P, WaveArea A, const LanePt &L,
                                          int lane, const Unit &U, const double *sE) {
   const double Et = sE[U.slot_lo];
-  const int nb = P.nb;
-  const bool lo_real = U.slot_lo >= 1, hi_real = U.slot_hi <= nb;
   const int wrapax[3] = {0, 0, 0};
-  uint32_t clo = 0, chi = 0;
+  uint32_t nhi = 0;
   double wlo = 0, whi = 0, rlo = 0, rhi = 0;
   stream_f64(U.pos, U.jb, U.je, [&](int j, double ux, double uy, double uz, double uw) {
     double dx, dy, dz;
     ref_sep<SHIFT, false>(L.x, L.y, L.z, ux, uy, uz, U.S, wrapax, 0.0, 0.0, dx, dy, dz);
     const double s64 = (dx * dx + dy * dy) + dz * dz;
     const bool hi = s64 >= Et;
-    const bool counted = hi_real || !hi;
-    if (!wave_any(counted)) return;
-    const double wj = counted ? uw : 0.0;
-    const double wr = wj * sep_sqrt(s64);
-    if (hi_real) {
-      chi += hi ? 1u : 0u;
-      clo += hi ? 0u : 1u;
-      whi += hi ? wj : 0.0;
-      rhi += hi ? wr : 0.0;
-      wlo += hi ? 0.0 : wj;
-      rlo += hi ? 0.0 : wr;
-    } else {
-      clo += counted ? 1u : 0u;
-      wlo += wj;
-      rlo += wr;
+    nhi += hi ? 1u : 0u;
+    if (HIREAL) {
+      const double r = sep_sqrt(s64);
+      const double a = hi ? uw : 0.0;
+      const double c = uw - a;   // exact: uw or 0
+      wlo += c;
+      rlo = __builtin_fma(c, r, rlo);
+      whi += a;
+      rhi = __builtin_fma(a, r, rhi);
+    } else if (!hi) {
+      wlo += uw;
+      rlo = __builtin_fma(uw, sep_sqrt(s64), rlo);
     }
   });
-  if (lo_real) {
-    atomicAdd(&A.hist[U.slot_lo * 64 + lane], clo);
-    atomicAdd(&A.hw[U.slot_lo * kWStripe + (lane & (kWStripe - 1))], L.w * wlo);
-    atomicAdd(&A.hwr[U.slot_lo * kWStripe + (lane & (kWStripe - 1))], L.w * rlo);
+  const uint32_t nlo = (uint32_t)(U.je - U.jb) - nhi;
+  if (U.slot_lo >= 1) {
+    atomicAdd(&A.hist[U.slot_lo * 64 + lane], nlo);
+    add_w(A.hw + 2 * (U.slot_lo * kWStripe + (lane & (kWStripe - 1))), L.w * wlo, L.w * rlo);
   }
-  if (hi_real) {
-    atomicAdd(&A.hist[U.slot_hi * 64 + lane], chi);
-    atomicAdd(&A.hw[U.slot_hi * kWStripe + (lane & (kWStripe - 1))], L.w * whi);
-    atomicAdd(&A.hwr[U.slot_hi * kWStripe + (lane & (kWStripe - 1))], L.w * rhi);
+  if (HIREAL) {
+    atomicAdd(&A.hist[U.slot_hi * 64 + lane], nhi);
+    add_w(A.hw + 2 * (U.slot_hi * kWStripe + (lane & (kWStripe - 1))), L.w * whi, L.w * rhi);
   }
 }
 
@@ -654,29 +621,25 @@ __device__ inline void loop_f64(const PairParams &P, WaveArea A, const LanePt &L
       const double s64 = rp2 + dz * dz;
       bool inr = s64 < EB;
       if (OWN) inr = inr && (j > L.iloc);
-      if (!wave_any(inr)) return;
       if (inr) {
         const int slot = slot64(tab64, lo, hi, sh, sE, nb, s64);
         atomicAdd(&A.hist[slot * 64 + lane], 1u);
         if (W) {
           const double ww = L.w * uw;
-          atomicAdd(&A.hw[slot * kWStripe + (lane & (kWStripe - 1))], ww);
-          atomicAdd(&A.hwr[slot * kWStripe + (lane & (kWStripe - 1))], ww * sep_sqrt(s64));
+          add_w(A.hw + 2 * (slot * kWStripe + (lane & (kWStripe - 1))), ww, ww * sep_sqrt(s64));
         }
       }
     } else {
       const double pz64 = fabs(dz);
       bool inr = (rp2 < EB) && (pz64 < P.pimax);
       if (OWN) inr = inr && (j > L.iloc);
-      if (!wave_any(inr)) return;
       if (inr) {
         const int slot = slot64(tab64, lo, hi, sh, sE, nb, rp2);
         const int l = exact_pibin(pz64, P.dpi, npi);
         atomicAdd(&A.hist[slot * npi + l], 1u);
         if (W) {
           const double ww = L.w * uw;
-          atomicAdd(&A.hw[slot * npi + l], ww);
-          atomicAdd(&A.hwr[slot * npi + l], ww * sep_sqrt(rp2));
+          add_w(A.hw + 2 * (slot * npi + l), ww, ww * sep_sqrt(rp2));
         }
       }
     }
@@ -711,8 +674,10 @@ __host__ __device__ inline LdsLayout lds_layout(int mode, int prec, int weighted
   return L;
 }
 
+// Weighted xi always runs in binary64 (the host routes it there), so
+// <XI, F32R, 1> is not instantiated.
 template <int MODE, int PREC, int W>
-__global__ __launch_bounds__(256) void k_pairs(PairParams P) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_pairs(PairParams P) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int lane = threadIdx.x & 63;
   const int wid = threadIdx.x >> 6;
@@ -729,15 +694,14 @@ __global__ __launch_bounds__(256) void k_pairs(PairParams P) {
   WaveArea A;
   A.hist = (uint32_t *)wb;
   A.hw = (double *)(wb + LY.wave_hist);
-  A.hwr = (double *)(wb + LY.wave_hist + LY.wave_w);
   const int NS = P.nslots;
   const int hwords = MODE == XI ? NS * 64 : NS * P.npi;
   const int wwords = MODE == XI ? NS * kWStripe : hwords;
   for (int t = lane; t < hwords; t += 64) A.hist[t] = 0u;
   if (W) {
     for (int t = lane; t < wwords; t += 64) {
-      A.hw[t] = 0.0;
-      A.hwr[t] = 0.0;
+      A.hw[2 * t] = 0.0;
+      A.hw[2 * t + 1] = 0.0;
     }
   }
   __syncthreads();
@@ -872,8 +836,8 @@ __global__ __launch_bounds__(256) void k_pairs(PairParams P) {
           packed = X | (Y << 10) | (Z << 20) | (own << 30);
         }
       }
-      unsigned long long mk = __ballot(keep != 0);
-      st_pruned += __popcll(__ballot(pruned != 0));
+      unsigned long long mk = __builtin_amdgcn_ballot_w64(keep != 0);
+      st_pruned += __popcll(__builtin_amdgcn_ballot_w64(pruned != 0));
       while (mk) {
         const int src = __builtin_ctzll(mk);
         mk &= mk - 1;
@@ -922,27 +886,22 @@ __global__ __launch_bounds__(256) void k_pairs(PairParams P) {
             const float ra = __builtin_fmaf(rzf, rzf, __builtin_fmaf(ryf, ryf, rxf * rxf));
             if (two) {
               if (valid) {
-                if (W) {
-                  if (shifted) loop_xi_f32_two_w<true>(P, A, L, lane, rxf, ryf, rzf, ra, U, sE, nrechk);
-                  else loop_xi_f32_two_w<false>(P, A, L, lane, rxf, ryf, rzf, ra, U, sE, nrechk);
-                } else {
-                  if (shifted) loop_xi_f32_two<true>(P, A, L, lane, rxf, ryf, rzf, ra, U, sE, nrechk);
-                  else loop_xi_f32_two<false>(P, A, L, lane, rxf, ryf, rzf, ra, U, sE, nrechk);
-                }
+                if (shifted) loop_xi_f32_two<true>(P, A, L, lane, rxf, ryf, rzf, ra, U, sE, nrechk);
+                else loop_xi_f32_two<false>(P, A, L, lane, rxf, ryf, rzf, ra, U, sE, nrechk);
               }
             } else {
-#define CP_XI(O, SH)                                                                     \
-  do {                                                                                   \
-    if (W) loop_xi_f32_w<O, SH>(P, A, L, lane, rxf, ryf, rzf, ra, U, tab32, sE, nrechk); \
-    else loop_xi_f32<O, SH>(P, A, L, lane, rxf, ryf, rzf, ra, U, tab32, sE, nrechk);     \
-  } while (0)
+#define CP_XI(O, SH) loop_xi_f32<O, SH>(P, A, L, lane, rxf, ryf, rzf, ra, U, tab32, sE, nrechk)
               if (own) { if (shifted) CP_XI(true, true); else CP_XI(true, false); }
               else { if (shifted) CP_XI(false, true); else CP_XI(false, false); }
 #undef CP_XI
             }
           } else {
             const float ra = __builtin_fmaf(ryf, ryf, rxf * rxf);
-#define CP_WP(O, SH) loop_wp_f32<O, SH, W>(P, A, L, lane, rxf, ryf, rzf, ra, U, tab32, sE, nrechk)
+#define CP_WP(O, SH)                                                                       \
+  do {                                                                                     \
+    if (W) loop_wp_f32_w<O, SH>(P, A, L, lane, rxf, ryf, rzf, ra, U, tab32, sE, nrechk);   \
+    else loop_wp_f32<O, SH>(P, A, L, lane, rxf, ryf, rzf, ra, U, tab32, sE, nrechk);       \
+  } while (0)
             if (own) { if (shifted) CP_WP(true, true); else CP_WP(true, false); }
             else { if (shifted) CP_WP(false, true); else CP_WP(false, false); }
 #undef CP_WP
@@ -950,8 +909,13 @@ __global__ __launch_bounds__(256) void k_pairs(PairParams P) {
         } else if (two) {
           if (valid) {
             if (W) {
-              if (shifted) loop_xi_f64_two_w<true>(P, A, L, lane, U, sE);
-              else loop_xi_f64_two_w<false>(P, A, L, lane, U, sE);
+              if (U.slot_hi <= P.nb) {
+                if (shifted) loop_xi_f64_two_w<true, true>(P, A, L, lane, U, sE);
+                else loop_xi_f64_two_w<false, true>(P, A, L, lane, U, sE);
+              } else {
+                if (shifted) loop_xi_f64_two_w<true, false>(P, A, L, lane, U, sE);
+                else loop_xi_f64_two_w<false, false>(P, A, L, lane, U, sE);
+              }
             } else {
               if (shifted) loop_xi_f64_two<true>(P, A, L, lane, U, sE);
               else loop_xi_f64_two<false>(P, A, L, lane, U, sE);
@@ -982,7 +946,6 @@ __global__ __launch_bounds__(256) void k_pairs(PairParams P) {
 }
 
 template __global__ void k_pairs<XI, F32R, 0>(PairParams);
-template __global__ void k_pairs<XI, F32R, 1>(PairParams);
 template __global__ void k_pairs<XI, F64, 0>(PairParams);
 template __global__ void k_pairs<XI, F64, 1>(PairParams);
 template __global__ void k_pairs<WP, F32R, 0>(PairParams);
