@@ -820,6 +820,7 @@ static int run(const Call &c, uint64_t *npairs, double *wsum, double *ravg) {
   P.tiles = S1.tiles;
   P.ntiles = S1.coloff + ncol;
   P.qhead = d_qhead;
+  P.nsplit = 2 * g.r[0] + 1;
   P.geom1 = &d_sm->geom[0];
   P.geom2 = &d_sm->geom[1];
   P.pos1 = S1.pos;
@@ -880,7 +881,7 @@ static int run(const Call &c, uint64_t *npairs, double *wsum, double *ravg) {
   HIPCHK(hipEventRecord(ev[3], st));
   HIPCHK(hipStreamSynchronize(st));
   if ((rc = map_err_flags(eflag))) return rc;
-  if (hst[4] < (unsigned long long)ntiles)
+  if (hst[4] < (unsigned long long)ntiles * (unsigned long long)P.nsplit)
     return fail(CP_ERR_INTERNAL, "work queue not drained");
 
   const double mult = (autoc && o.count_mode == CP_ORDERED) ? 2.0 : 1.0;
@@ -1170,6 +1171,7 @@ static int batch_upload(cp_plan &pl, Batch &b) {
   P.tiles = b.S.tiles;
   P.ntiles = b.S.coloff + b.ncol_tot;
   P.qhead = b.d_stats + 4;
+  P.nsplit = 2 * b.g.r[0] + 1;
   P.geom1 = b.d_geom;
   P.geom2 = b.d_geom;
   P.pos1 = b.S.pos;

@@ -69,6 +69,8 @@ struct PairParams {
   const Tile *tiles;
   const int *ntiles;         // device: number of tiles in the queue
   unsigned long long *qhead;
+  int nsplit;                // queue items per tile: one per x offset of the
+                             // neighbour search (2 r_x + 1 slabs)
   // geometry (indexed by tile.mock); set 2 is the searched (streamed) set
   const GridGeom *geom1;
   const GridGeom *geom2;

@@ -708,7 +708,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
 
   unsigned long long st_cand = 0, st_cells = 0, st_pruned = 0;
   uint32_t nrechk = 0;
-  const int64_t ntiles = *P.ntiles;
+  const int64_t nsplit = P.nsplit;
+  const int64_t nitems = (int64_t)*P.ntiles * nsplit;
   int cur_mock = -1;
   unsigned long long since_flush = 0;
   const unsigned long long flush_limit = MODE == XI ? (1ull << 30) : (1ull << 24);
@@ -717,8 +718,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
     int64_t tix = 0;
     if (lane == 0) tix = (int64_t)atomicAdd(P.qhead, 1ull);
     tix = uni64(__shfl(tix, 0));
-    if (tix >= ntiles) break;
-    const Tile T = P.tiles[tix];
+    if (tix >= nitems) break;
+    // item = (tile, x offset of the neighbour search): consecutive items
+    // share a tile, so its slabs run on different waves at the same time
+    const int64_t tile_ix = tix / nsplit;
+    const int part = (int)(tix - tile_ix * nsplit);
+    const Tile T = P.tiles[tile_ix];
     const int mock = uni(T.mock);
     if (mock != cur_mock) {
       if (cur_mock >= 0) flush_hist<MODE, W>(P, A, cur_mock, lane);
@@ -752,7 +757,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
     const int rx = G2.r[0], ry = G2.r[1], rz = G2.r[2];
     const int nzr = (tz1 - tz0) + 2 * rz + 1;
     const int ncy = 2 * ry + 1;
-    const int total = (2 * rx + 1) * ncy * nzr;
+    const int total = part <= 2 * rx ? ncy * nzr : 0;
     const double box = G2.box, half = G2.halfbox;
     const int wrapax[3] = {G2.wrap[0], G2.wrap[1], G2.wrap[2]};
     const bool anywrap = wrapax[0] | wrapax[1] | wrapax[2];
@@ -763,9 +768,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
       int keep = 0, pruned = 0, cell = 0, packed = 0, slots = 0;
       if (t < total) {
         const int oz = t % nzr;
-        const int rest = t / nzr;
-        const int oy = rest % ncy;
-        const int ox = rest / ncy;
+        const int oy = t / nzr;
+        const int ox = part;
         int X = cx + ox - rx, Y = cy + oy - ry, Z = tz0 - rz + oz;
         int sx = 0, sy = 0, sz = 0;
         bool ok = true;
