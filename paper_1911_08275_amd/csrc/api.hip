@@ -32,6 +32,10 @@ __global__ void k_assign(const PointsDev *pts, const GridGeom *geom, int *cell_c
                          int *rank, int *err);
 __global__ void k_scatter(const PointsDev *pts, const GridGeom *geom, const int *cstart,
                           const int *cid, const int *rank, double4 *pos, float4 *strm, int mode);
+__global__ void k_group(const PointsDev *pts, const GridGeom *geom, const int *cstart,
+                        const int *cid, const int *rank, int *idx, double *zs);
+__global__ void k_zrank(const GridGeom *geom, int nmock, const int *cstart, const int *idx,
+                        const double *zs, int *rank, const int64_t *cell_prefix);
 __global__ void k_cellbox(const GridGeom *geom, int nmock, const int *cstart, const double4 *pos,
                           CellBox *cbox, const int64_t *cell_prefix);
 __global__ void k_tiles(const GridGeom *geom, int nmock, const int *cstart, const int *maxspan,
@@ -458,14 +462,20 @@ static int launch_build(hipStream_t st, const PointsDev *d_pts, const GridGeom *
                        S.rank, d_err);
   hipLaunchKernelGGL(k_scan_segments, dim3(1), dim3(1024), 0, st, S.ccount, S.cstart,
                      d_seg_cells);
-  if (n > 0)
+  if (n > 0) {
+    hipLaunchKernelGGL(k_group, dim3(ab, 1), dim3(256), 0, st, d_pts, d_geom, S.cstart, S.cid,
+                       S.rank, (int *)S.strm, (double *)S.pos);
+    const int zb = (int)std::min<int64_t>(std::max<int64_t>((ncell + 3) / 4, 1), 16384);
+    hipLaunchKernelGGL(k_zrank, dim3(zb), dim3(256), 0, st, d_geom, 1, S.cstart,
+                       (const int *)S.strm, (const double *)S.pos, S.rank, d_cell_prefix);
     hipLaunchKernelGGL(k_scatter, dim3(ab, 1), dim3(256), 0, st, d_pts, d_geom, S.cstart, S.cid,
                        S.rank, S.pos, S.strm, mode);
+  }
   const int cb = (int)std::min<int64_t>(std::max<int64_t>((ncell + 3) / 4, 1), 16384);
   hipLaunchKernelGGL(k_cellbox, dim3(cb), dim3(256), 0, st, d_geom, 1, S.cstart, S.pos, S.cbox,
                      d_cell_prefix);
   if (tiles) {
-    const int tb = (int)std::max<int64_t>((ncol + 255) / 256, 1);
+    const int tb = (int)std::min<int64_t>(std::max<int64_t>((ncol + 3) / 4, 1), 16384);
     hipLaunchKernelGGL(k_tiles, dim3(tb), dim3(256), 0, st, d_geom, 1, S.cstart, d_maxspan,
                        d_col_prefix, S.colcnt, S.coloff, S.tiles, 0);
     hipLaunchKernelGGL(k_scan_segments, dim3(1), dim3(1024), 0, st, S.colcnt, S.coloff,
@@ -734,7 +744,7 @@ static int run(const Call &c, uint64_t *npairs, double *wsum, double *ravg) {
     hist = cv.take<unsigned long long>(nout);
     hw = cv.take<double>(nout);
     hwr = cv.take<double>(nout);
-    stats = cv.take<unsigned long long>(5);   // 4 counters + queue head
+    stats = cv.take<unsigned long long>(6);   // 4 counters, queue head, tile count
     qhead = stats + 4;
     err = cv.take<int>(1);
   };
@@ -789,16 +799,26 @@ static int run(const Call &c, uint64_t *npairs, double *wsum, double *ravg) {
   hs.col_prefix[0] = 0;
   hs.col_prefix[1] = ncol;
   hs.maxspan[0] = g.maxspan;
-  HIPCHK(hipMemcpyAsync(d_sm, &hs, sizeof(hs), hipMemcpyHostToDevice, st));
-  if (n32) HIPCHK(hipMemcpyAsync(d_t32, B.t32.e.data(), n32 * 8, hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemcpyAsync(d_t64, B.t64.e.data(), n64 * 8, hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemcpyAsync(d_E, B.E.data(), c.nedges * 8, hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemcpyAsync(d_c32, B.C32.data(), c.nedges * 4, hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemcpyAsync(d_a32, B.A32.data(), c.nedges * 4, hipMemcpyHostToDevice, st));
+  {
+    // the small records and tables are carved consecutively: one upload
+    char *up0 = (char *)d_sm;
+    const size_t upn = (size_t)((char *)(d_a32 + c.nedges) - up0);
+    std::vector<char> hup(upn, 0);
+    auto put = [&](const void *dev, const void *src, size_t bytes) {
+      if (bytes) memcpy(hup.data() + ((const char *)dev - up0), src, bytes);
+    };
+    put(d_sm, &hs, sizeof(hs));
+    put(d_t32, B.t32.e.data(), (size_t)n32 * 8);
+    put(d_t64, B.t64.e.data(), (size_t)n64 * 8);
+    put(d_E, B.E.data(), (size_t)c.nedges * 8);
+    put(d_c32, B.C32.data(), (size_t)c.nedges * 4);
+    put(d_a32, B.A32.data(), (size_t)c.nedges * 4);
+    HIPCHK(hipMemcpyAsync(up0, hup.data(), upn, hipMemcpyHostToDevice, st));
+  }
   hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(256), 0, st, d_hist, (int64_t)nout);
   hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(256), 0, st, d_hw, (int64_t)nout);
   hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(256), 0, st, d_hwr, (int64_t)nout);
-  hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, d_stats, (int64_t)5);  // stats + qhead
+  hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, d_stats, (int64_t)6);
   hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, d_err, (int64_t)1, 0);
 
   // ---- cell build
@@ -864,22 +884,29 @@ static int run(const Call &c, uint64_t *npairs, double *wsum, double *ravg) {
   if ((rc = launch_pairs(st, c.mode, prec, weighted, P, lds, nwaves))) return rc;
   HIPCHK(hipEventRecord(ev[2], st));
 
-  // ---- results
+  // ---- results: histogram, weight sums, statistics and the error flag are
+  // carved consecutively, so one download brings them all
   std::vector<unsigned long long> h(nout);
   std::vector<double> hwv(nout), hwrv(nout);
-  unsigned long long hst[5];
+  unsigned long long hst[6];
   int eflag = 0;
-  int ntiles = 0;
-  HIPCHK(hipMemcpyAsync(h.data(), d_hist, 8 * nout, hipMemcpyDeviceToHost, st));
-  if (weighted) {
-    HIPCHK(hipMemcpyAsync(hwv.data(), d_hw, 8 * nout, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(hwrv.data(), d_hwr, 8 * nout, hipMemcpyDeviceToHost, st));
-  }
-  HIPCHK(hipMemcpyAsync(hst, d_stats, sizeof(hst), hipMemcpyDeviceToHost, st));
-  HIPCHK(hipMemcpyAsync(&eflag, d_err, sizeof(int), hipMemcpyDeviceToHost, st));
-  HIPCHK(hipMemcpyAsync(&ntiles, S1.coloff + ncol, sizeof(int), hipMemcpyDeviceToHost, st));
+  char *dn0 = (char *)d_hist;
+  const size_t dnn = (size_t)((char *)(d_err + 1) - dn0);
+  std::vector<char> hdn(dnn);
+  HIPCHK(hipMemcpyAsync(hdn.data(), dn0, dnn, hipMemcpyDeviceToHost, st));
   HIPCHK(hipEventRecord(ev[3], st));
   HIPCHK(hipStreamSynchronize(st));
+  auto get = [&](void *dst, const void *dev, size_t bytes) {
+    memcpy(dst, hdn.data() + ((const char *)dev - dn0), bytes);
+  };
+  get(h.data(), d_hist, 8 * (size_t)nout);
+  if (weighted) {
+    get(hwv.data(), d_hw, 8 * (size_t)nout);
+    get(hwrv.data(), d_hwr, 8 * (size_t)nout);
+  }
+  get(hst, d_stats, sizeof(hst));
+  get(&eflag, d_err, sizeof(int));
+  const int ntiles = (int)hst[5];
   if ((rc = map_err_flags(eflag))) return rc;
   if (hst[4] < (unsigned long long)ntiles * (unsigned long long)P.nsplit)
     return fail(CP_ERR_INTERNAL, "work queue not drained");
@@ -1016,7 +1043,7 @@ extern "C" size_t countpairs_workspace_size(int kind, int64_t n1, int64_t n2, co
   cv.take<unsigned long long>(nout);
   cv.take<double>(nout);
   cv.take<double>(nout);
-  cv.take<unsigned long long>(5);
+  cv.take<unsigned long long>(6);
   cv.take<int>(1);
   return cv.off + 256;
 }
@@ -1147,7 +1174,7 @@ static void batch_carve(Carver &cv, cp_plan &pl, Batch &b) {
   b.d_hist = cv.take<unsigned long long>((int64_t)b.nout * nm);
   b.d_hw = cv.take<double>(1);
   b.d_hwr = cv.take<double>(1);
-  b.d_stats = cv.take<unsigned long long>(5);
+  b.d_stats = cv.take<unsigned long long>(6);   // 4 counters, queue head, tile count
   b.d_err = cv.take<int>(1);
 }
 
@@ -1221,17 +1248,22 @@ static int batch_enqueue(cp_plan &pl, Batch &b, hipStream_t st) {
                      b.S.ccount, b.ncell_tot, 0);
   hipLaunchKernelGGL(k_fill_u64, dim3(blocks((int64_t)b.nout * nm, 256, 1024)), dim3(256), 0, st,
                      b.d_hist, (int64_t)b.nout * nm);
-  hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, b.d_stats, (int64_t)5);
+  hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, b.d_stats, (int64_t)6);
   hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, b.d_err, (int64_t)1, 0);
   hipLaunchKernelGGL(k_assign, dim3(blocks(pl.maxn, 256, 4096), nm), dim3(256), 0, st, b.d_pts,
                      b.d_geom, b.S.ccount, b.S.cid, b.S.rank, b.d_err);
   hipLaunchKernelGGL(k_scan_segments, dim3(nm), dim3(1024), 0, st, b.S.ccount, b.S.cstart,
                      b.d_segs);
+  hipLaunchKernelGGL(k_group, dim3(blocks(pl.maxn, 256, 4096), nm), dim3(256), 0, st, b.d_pts,
+                     b.d_geom, b.S.cstart, b.S.cid, b.S.rank, (int *)b.S.strm, (double *)b.S.pos);
+  hipLaunchKernelGGL(k_zrank, dim3(blocks(b.ncell_tot, 4, 65536)), dim3(256), 0, st, b.d_geom,
+                     nm, b.S.cstart, (const int *)b.S.strm, (const double *)b.S.pos, b.S.rank,
+                     b.d_cell_prefix);
   hipLaunchKernelGGL(k_scatter, dim3(blocks(pl.maxn, 256, 4096), nm), dim3(256), 0, st, b.d_pts,
                      b.d_geom, b.S.cstart, b.S.cid, b.S.rank, b.S.pos, b.S.strm, b.mode);
   hipLaunchKernelGGL(k_cellbox, dim3(blocks(b.ncell_tot, 4, 65536)), dim3(256), 0, st, b.d_geom,
                      nm, b.S.cstart, b.S.pos, b.S.cbox, b.d_cell_prefix);
-  const int tb = blocks(b.ncol_tot, 256, 65536);
+  const int tb = blocks(b.ncol_tot, 4, 65536);
   hipLaunchKernelGGL(k_tiles, dim3(tb), dim3(256), 0, st, b.d_geom, nm, b.S.cstart, b.d_maxspan,
                      b.d_col_prefix, b.S.colcnt, b.S.coloff, b.S.tiles, 0);
   hipLaunchKernelGGL(k_scan_segments, dim3(1), dim3(1024), 0, st, b.S.colcnt, b.S.coloff,

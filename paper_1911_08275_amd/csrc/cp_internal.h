@@ -12,6 +12,7 @@ constexpr int kMaxAxisCells = 1023; // cells per axis (packed in 10 bits)
 constexpr int kMaxBins = 60;        // separation bins; slots 0 and nb+1 are trash and
                                     // slot + 1 must fit the 6-bit table code
 constexpr int kMaxPiBins = 256;
+constexpr int kZSortMax = 4096;   // cells up to this many points are z-sorted
 constexpr int kWStripe = 8;       // copies of each weight sum per wave (lane & 7)
 
 enum Mode { XI = 0, WP = 1 };
@@ -104,7 +105,8 @@ struct PairParams {
   unsigned long long *hist;  // [nmock][nb * npi]
   double *hw;                // [nmock][nb * npi] sum of weights
   double *hwr;               // [nmock][nb * npi] sum of weight * separation
-  unsigned long long *stats; // candidates, rechecks, cellpairs, pruned
+  unsigned long long *stats; // candidates, rechecks, cell pairs, pruned, queue head,
+                             // tile count (written by the pair kernel)
   int hist_stride;           // nb * npi
 };
 

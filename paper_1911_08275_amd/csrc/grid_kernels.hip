@@ -105,30 +105,49 @@ struct ScanSeg {
 // chunk sums, then each thread writes its chunk.
 __global__ __launch_bounds__(1024) void k_scan_segments(const int *in, int *out,
                                                         const ScanSeg *segs) {
+  // Tiles of 4096 values: 4 consecutive values per thread, a shuffle scan
+  // inside each wave, the 16 wave totals scanned by wave 0, and a running
+  // carry from tile to tile.
   const ScanSeg S = segs[blockIdx.x];
   const int *src = in + S.in_off;
   int *dst = out + S.out_off;
-  const int64_t per = (S.len + blockDim.x - 1) / blockDim.x;
-  const int64_t b = per * threadIdx.x;
-  const int64_t e = b + per < S.len ? b + per : S.len;
-  int sum = 0;
-  for (int64_t i = b; i < e; i++) sum += src[i];
-  __shared__ int sh[1024];
-  sh[threadIdx.x] = sum;
-  __syncthreads();
-  for (int off = 1; off < (int)blockDim.x; off <<= 1) {
-    int v = (int)threadIdx.x >= off ? sh[threadIdx.x - off] : 0;
+  __shared__ int wsum[16];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  int carry = 0;
+  for (int64_t t0 = 0; t0 < S.len; t0 += 4096) {
+    const int64_t i0 = t0 + 4 * (int64_t)tid;
+    int v[4];
+#pragma unroll
+    for (int k = 0; k < 4; k++) v[k] = i0 + k < S.len ? src[i0 + k] : 0;
+    const int loc = (v[0] + v[1]) + (v[2] + v[3]);
+    int x = loc;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int y = __shfl_up(x, off);
+      if (lane >= off) x += y;
+    }
+    if (lane == 63) wsum[w] = x;
     __syncthreads();
-    sh[threadIdx.x] += v;
+    if (w == 0) {
+      int t = lane < 16 ? wsum[lane] : 0;
+#pragma unroll
+      for (int off = 1; off < 16; off <<= 1) {
+        const int y = __shfl_up(t, off);
+        if (lane >= off) t += y;
+      }
+      if (lane < 16) wsum[lane] = t;
+    }
+    __syncthreads();
+    int run = carry + (w > 0 ? wsum[w - 1] : 0) + (x - loc);
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      if (i0 + k < S.len) dst[i0 + k] = run;
+      run += v[k];
+    }
+    carry += wsum[15];
     __syncthreads();
   }
-  int run = sh[threadIdx.x] - sum;
-  for (int64_t i = b; i < e; i++) {
-    int v = src[i];
-    dst[i] = run;
-    run += v;
-  }
-  if (threadIdx.x == blockDim.x - 1) dst[S.len] = sh[threadIdx.x];
+  if (tid == 0) dst[S.len] = carry;
 }
 
 // --------------------------------------------------------- cell assignment
@@ -199,6 +218,96 @@ __global__ __launch_bounds__(256) void k_scatter(const PointsDev *pts, const Gri
   }
 }
 
+// z order inside each cell (ties by input index), so the pair kernel can
+// cut a unit down to the z-window its tile can reach (Section 2.2: late
+// entry and early exit on z-sorted cells).  k_group lists each cell's points
+// in the atomic order together with their z; k_zrank turns every point's rank
+// into its rank in z.  Both use the position and stream buffers as scratch
+// (k_scatter overwrites them).  Cells above kZSortMax points keep the atomic
+// order; the pair kernel searches those whole.
+__global__ __launch_bounds__(256) void k_group(const PointsDev *pts, const GridGeom *geom,
+                                               const int *cstart, const int *cid,
+                                               const int *rank, int *idx, double *zs) {
+  const PointsDev P = pts[blockIdx.y];
+  const GridGeom &G = geom[blockIdx.y];
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < P.n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int cell = cid[G.pbase + i];
+    const int64_t k = G.pbase + cstart[G.sbase + cell] + rank[G.pbase + i];
+    idx[k] = (int)i;
+    zs[k] = load_coord(P.z, P.dtype, i);
+  }
+}
+
+// One wave per cell: the cell's z values are staged in the wave's LDS slice,
+// kZChunk at a time, and each lane ranks NP of its points per broadcast scan
+// over them.  Ties in z are broken by the grouped position, which makes the
+// ranks a permutation (counts do not depend on the order inside a cell).
+constexpr int kZChunk = 1024;
+
+template <int NP>
+__device__ inline void zrank_pass(const double *zs, const int *idx, int64_t base, int64_t pbase,
+                                  int n, int q0, int lane, double *zw, int *rank) {
+  double zi[NP];
+  int kq[NP], r[NP];
+#pragma unroll
+  for (int p = 0; p < NP; p++) {
+    kq[p] = q0 + p * 64 + lane;
+    zi[p] = kq[p] < n ? zs[base + kq[p]] : 0.0;
+    r[p] = 0;
+  }
+  for (int c0 = 0; c0 < n; c0 += kZChunk) {
+    const int cnt = min(kZChunk, n - c0);
+    if (q0 == 0 || n > kZChunk) {   // (re)stage this chunk
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      for (int t = lane; t < cnt; t += 64) zw[t] = zs[base + c0 + t];
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+    }
+#pragma unroll 4
+    for (int t = 0; t < cnt; t++) {
+      const double zj = zw[t];
+#pragma unroll
+      for (int p = 0; p < NP; p++) r[p] += (zj < zi[p] || (zj == zi[p] && c0 + t < kq[p])) ? 1 : 0;
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < NP; p++)
+    if (kq[p] < n) rank[pbase + idx[base + kq[p]]] = r[p];
+}
+
+__global__ __launch_bounds__(256) void k_zrank(const GridGeom *geom, int nmock,
+                                               const int *cstart, const int *idx,
+                                               const double *zs, int *rank,
+                                               const int64_t *cell_prefix) {
+  __shared__ double zsh[4][kZChunk];
+  const int w = threadIdx.x >> 6;
+  const int wid = (int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6);
+  const int lane = threadIdx.x & 63;
+  double *zw = zsh[w];
+  const int64_t total = cell_prefix[nmock];
+  for (int64_t gc = wid; gc < total; gc += (int64_t)gridDim.x * (blockDim.x >> 6)) {
+    int lo = 0, hi = nmock - 1;
+    while (lo < hi) {
+      int mid = (lo + hi + 1) >> 1;
+      if (cell_prefix[mid] <= gc) lo = mid; else hi = mid - 1;
+    }
+    const GridGeom &G = geom[lo];
+    const int c = (int)(gc - cell_prefix[lo]);
+    const int b = cstart[G.sbase + c], e = cstart[G.sbase + c + 1];
+    const int n = e - b;
+    if (n <= 1 || n > kZSortMax) continue;   // one point: rank 0 already
+    const int64_t base = G.pbase + b;
+    if (n <= 64) {
+      zrank_pass<1>(zs, idx, base, G.pbase, n, 0, lane, zw, rank);
+    } else {
+      for (int q0 = 0; q0 < n; q0 += 4 * 64)
+        zrank_pass<4>(zs, idx, base, G.pbase, n, q0, lane, zw, rank);
+    }
+  }
+}
+
 // Per-cell bounding boxes (binary64), one wave per cell.
 __global__ __launch_bounds__(256) void k_cellbox(const GridGeom *geom, int nmock,
                                                  const int *cstart, const double4 *pos,
@@ -248,21 +357,21 @@ __global__ __launch_bounds__(256) void k_cellbox(const GridGeom *geom, int nmock
 // maxspan z-cells, so every lane holds a point whenever the column allows.
 // emit = 0: count tiles per column; emit = 1: write them at the offsets of
 // the scanned counts.
-__device__ inline void walk_column(const GridGeom &G, const int *cstart, int col, int maxspan,
+__device__ inline void walk_column(const GridGeom &G, const int *cs, int col, int maxspan,
                                    int mock, int emit, Tile *out, int64_t &ntile) {
+  // cs[z] = start of z-cell z of the column (z = 0..nz), relative to the set
   const int nz = G.n[2];
-  const int c0 = col * nz;
-  const int pend = cstart[G.sbase + c0 + nz];
-  int p = cstart[G.sbase + c0];
+  const int pend = cs[nz];
+  int p = cs[0];
   int z = 0;   // cell of point p
   while (p < pend) {
-    while (cstart[G.sbase + c0 + z + 1] <= p) z++;
+    while (cs[z + 1] <= p) z++;
     // furthest cell allowed by the span limit, and its end
     const int zmax = min(nz - 1, z + maxspan - 1);
-    const int lim = cstart[G.sbase + c0 + zmax + 1];
+    const int lim = cs[zmax + 1];
     const int q = min(p + kTileMax, lim);
     int z1 = z;
-    while (cstart[G.sbase + c0 + z1 + 1] < q) z1++;
+    while (cs[z1 + 1] < q) z1++;
     if (emit) {
       Tile T;
       T.p0 = G.pbase + p;
@@ -279,13 +388,18 @@ __device__ inline void walk_column(const GridGeom &G, const int *cstart, int col
   }
 }
 
+// One wave per column: the column's cell starts are staged in the wave's LDS
+// slice, then one lane walks them.
 __global__ __launch_bounds__(256) void k_tiles(const GridGeom *geom, int nmock,
                                                const int *cstart, const int *maxspan,
                                                const int64_t *col_prefix, int *colcnt,
                                                const int *coloff, Tile *tiles, int emit) {
+  __shared__ int csh[4][kMaxAxisCells + 1];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  int *cs = csh[w];
   const int64_t total = col_prefix[nmock];
-  for (int64_t gcol = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gcol < total;
-       gcol += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t gcol = wid; gcol < total; gcol += (int64_t)gridDim.x * (blockDim.x >> 6)) {
     int lo = 0, hi = nmock - 1;
     while (lo < hi) {
       int mid = (lo + hi + 1) >> 1;
@@ -293,9 +407,17 @@ __global__ __launch_bounds__(256) void k_tiles(const GridGeom *geom, int nmock,
     }
     const GridGeom &G = geom[lo];
     const int col = (int)(gcol - col_prefix[lo]);
-    int64_t n = emit ? coloff[gcol] : 0;
-    walk_column(G, cstart, col, maxspan[lo], lo, emit, tiles, n);
-    if (!emit) colcnt[gcol] = (int)n;
+    const int nz = G.n[2];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    for (int z = lane; z <= nz; z += 64) cs[z] = cstart[G.sbase + col * nz + z];
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    if (lane == 0) {
+      int64_t n = emit ? coloff[gcol] : 0;
+      walk_column(G, cs, col, maxspan[lo], lo, emit, tiles, n);
+      if (!emit) colcnt[gcol] = (int)n;
+    }
   }
 }
 

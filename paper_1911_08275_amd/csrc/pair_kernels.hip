@@ -333,6 +333,38 @@ __device__ inline void stream_w(const float4 *fbase, const double4 *dbase, int j
   }
 }
 
+// Narrows the records [jb, je) of a z-sorted cell to those with
+// zlo <= z <= zhi: two lane-parallel searches, 64 records per step, the
+// first from the front for the lower end, the second from the back for the
+// upper end.  jb, je and the result are wave-uniform.
+__device__ inline void zwindow(const double4 *pos, float zlo, float zhi, int lane, int &jb,
+                               int &je) {
+  const double *zp = (const double *)pos + 2;   // z of record j at zp[4 j]
+  const double lo = (double)zlo, hi = (double)zhi;
+  int b = je;
+  for (int j0 = jb; j0 < je; j0 += 64) {
+    const int j = j0 + lane;
+    const bool ge = j < je && zp[4 * j] >= lo;
+    const unsigned long long m = __builtin_amdgcn_ballot_w64(ge);
+    if (m) {
+      b = j0 + __builtin_ctzll(m);
+      break;
+    }
+  }
+  int e = b;
+  for (int j1 = je; j1 > b; j1 -= 64) {
+    const int j = j1 - 64 + lane;
+    const bool le = j >= b && zp[4 * j] <= hi;
+    const unsigned long long m = __builtin_amdgcn_ballot_w64(le);
+    if (m) {
+      e = j1 - 64 + (63 - __builtin_clzll(m)) + 1;
+      break;
+    }
+  }
+  jb = b;
+  je = e;
+}
+
 // Per-unit data handed to the inner loops.
 struct Unit {
   int jb, je;             // streamed records, relative to the catalogue's first point
@@ -709,7 +741,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
   unsigned long long st_cand = 0, st_cells = 0, st_pruned = 0;
   uint32_t nrechk = 0;
   const int64_t nsplit = P.nsplit;
-  const int64_t nitems = (int64_t)*P.ntiles * nsplit;
+  const int64_t ntiles = *P.ntiles;
+  const int64_t nitems = ntiles * nsplit;
+  if (blockIdx.x == 0 && threadIdx.x == 0) P.stats[5] = (unsigned long long)ntiles;
   int cur_mock = -1;
   unsigned long long since_flush = 0;
   const unsigned long long flush_limit = MODE == XI ? (1ull << 30) : (1ull << 24);
@@ -765,7 +799,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
 
     for (int base = 0; base < total; base += 64) {
       const int t = base + lane;
-      int keep = 0, pruned = 0, cell = 0, packed = 0, slots = 0;
+      int keep = 0, pruned = 0, cell = 0, packed = 0, slots = 0, win = 0, wzlo = 0, wzhi = 0;
       if (t < total) {
         const int oz = t % nzr;
         const int oy = t / nzr;
@@ -827,16 +861,40 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
             if (far) {
               ok = false;
               pruned = 1;
-            } else if (MODE == XI) {
-              const double slo = rp + m[2] * m[2];
-              const double shi = (M[0] * M[0] + M[1] * M[1]) + M[2] * M[2];
-              slots = exact_slot(sE, P.nb, slo) | (exact_slot(sE, P.nb, shi) << 8);
+            } else {
+              if (MODE == XI) {
+                const double slo = rp + m[2] * m[2];
+                const double shi = (M[0] * M[0] + M[1] * M[1]) + M[2] * M[2];
+                slots = exact_slot(sE, P.nb, slo) | (exact_slot(sE, P.nb, shi) << 8);
+              }
+              // z-window of the unit in the cell's own coordinates (Section
+              // 2.2, late entry / early exit): a pair within reach has
+              // |dz| <= hz, so only the cell's z-sorted points in
+              // [zmin_tile - S - hz, zmax_tile - S + hz] can pair; the slack
+              // terms cover binary64 rounding many times over.
+              if (!anywrap && e - b <= kZSortMax) {
+                // (binary32 square root with a 1e-5 relative allowance: the
+                // window needs no more precision and stays free of binary64
+                // FMAs)
+                double hz = MODE == XI
+                                ? (double)sqrtf((float)(fmax(P.EB - rp, 0.0) + 1e-12 * P.EB)) *
+                                      (1.0 + 1e-5)
+                                : P.pimax * (1.0 + 1e-9);
+                hz = hz + 1e-9 * (fabs(blz) + fabs(bhz) + fabs(S2) + 1.0);
+                const double zl = blz - S2 - hz, zh = bhz - S2 + hz;
+                if (zl > B.lo[2] || zh < B.hi[2]) {
+                  win = 1;
+                  wzlo = __float_as_int(__double2float_rd(zl));
+                  wzhi = __float_as_int(__double2float_ru(zh));
+                }
+              }
             }
           }
         }
         if (ok) {
-          // shift code per axis (-1, 0, +1 -> 0, 1, 2) in bits 1..6 of keep
-          keep = 1 | ((sx + 1) << 1) | ((sy + 1) << 3) | ((sz + 1) << 5);
+          // shift code per axis (-1, 0, +1 -> 0, 1, 2) in bits 1..6 of keep,
+          // z-window flag in bit 7
+          keep = 1 | ((sx + 1) << 1) | ((sy + 1) << 3) | ((sz + 1) << 5) | (win << 7);
           packed = X | (Y << 10) | (Z << 20) | (own << 30);
         }
       }
@@ -864,6 +922,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
         U.je = CS[G2.sbase + c2 + 1];
         U.slot_lo = sl & 255;
         U.slot_hi = (sl >> 8) & 255;
+        if (kc & 128) {
+          const float zlo = __int_as_float(__builtin_amdgcn_readlane(wzlo, src));
+          const float zhi = __int_as_float(__builtin_amdgcn_readlane(wzhi, src));
+          zwindow(U.pos, zlo, zhi, lane, U.jb, U.je);
+          if (U.je <= U.jb) continue;
+        }
         const unsigned long long nj = (unsigned long long)(U.je - U.jb);
         st_cells++;
         since_flush += nj;
