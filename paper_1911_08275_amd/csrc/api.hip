@@ -30,14 +30,11 @@ struct ScanSeg {
 __global__ void k_scan_segments(const int *in, int *out, const ScanSeg *segs);
 __global__ void k_assign(const PointsDev *pts, const GridGeom *geom, int *cell_count, int *cid,
                          int *rank, int *err);
-__global__ void k_scatter(const PointsDev *pts, const GridGeom *geom, const int *cstart,
-                          const int *cid, const int *rank, double4 *pos, float4 *strm, int mode);
 __global__ void k_group(const PointsDev *pts, const GridGeom *geom, const int *cstart,
-                        const int *cid, const int *rank, int *idx, double *zs);
-__global__ void k_zrank(const GridGeom *geom, int nmock, const int *cstart, const int *idx,
-                        const double *zs, int *rank, const int64_t *cell_prefix);
-__global__ void k_cellbox(const GridGeom *geom, int nmock, const int *cstart, const double4 *pos,
-                          CellBox *cbox, const int64_t *cell_prefix);
+                        const int *cid, const int *rank, double4 *grp);
+__global__ void k_cellfin(const GridGeom *geom, int nmock, const int *cstart, const double4 *grp,
+                          double4 *pos, float4 *strm, CellBox *cbox, const int64_t *cell_prefix,
+                          int mode);
 __global__ void k_tiles(const GridGeom *geom, int nmock, const int *cstart, const int *maxspan,
                         const int64_t *col_prefix, int *colcnt, const int *coloff, Tile *tiles,
                         int emit);
@@ -352,7 +349,7 @@ struct Carver {
 // Device buffers of one gridded point set.
 struct SetBufs {
   int *ccount, *cstart, *cid, *rank, *colcnt, *coloff;
-  double4 *pos;
+  double4 *pos, *grp;   // grp: points grouped by cell before the z order
   float4 *strm;
   CellBox *cbox;
   Tile *tiles;
@@ -366,6 +363,7 @@ static void carve_set(Carver &cv, SetBufs &S, int64_t n, int64_t ncell, int64_t 
   S.rank = cv.take<int>(n > 0 ? n : 1);
   // +8 records: the pair kernels prefetch scalar loads past a cell's end
   S.pos = cv.take<double4>(n + 8);
+  S.grp = cv.take<double4>(n > 0 ? n : 1);
   S.strm = cv.take<float4>(n + 8);
   S.cbox = cv.take<CellBox>(ncell);
   if (want_tiles) {
@@ -462,18 +460,12 @@ static int launch_build(hipStream_t st, const PointsDev *d_pts, const GridGeom *
                        S.rank, d_err);
   hipLaunchKernelGGL(k_scan_segments, dim3(1), dim3(1024), 0, st, S.ccount, S.cstart,
                      d_seg_cells);
-  if (n > 0) {
+  if (n > 0)
     hipLaunchKernelGGL(k_group, dim3(ab, 1), dim3(256), 0, st, d_pts, d_geom, S.cstart, S.cid,
-                       S.rank, (int *)S.strm, (double *)S.pos);
-    const int zb = (int)std::min<int64_t>(std::max<int64_t>((ncell + 3) / 4, 1), 16384);
-    hipLaunchKernelGGL(k_zrank, dim3(zb), dim3(256), 0, st, d_geom, 1, S.cstart,
-                       (const int *)S.strm, (const double *)S.pos, S.rank, d_cell_prefix);
-    hipLaunchKernelGGL(k_scatter, dim3(ab, 1), dim3(256), 0, st, d_pts, d_geom, S.cstart, S.cid,
-                       S.rank, S.pos, S.strm, mode);
-  }
+                       S.rank, S.grp);
   const int cb = (int)std::min<int64_t>(std::max<int64_t>((ncell + 3) / 4, 1), 16384);
-  hipLaunchKernelGGL(k_cellbox, dim3(cb), dim3(256), 0, st, d_geom, 1, S.cstart, S.pos, S.cbox,
-                     d_cell_prefix);
+  hipLaunchKernelGGL(k_cellfin, dim3(cb), dim3(256), 0, st, d_geom, 1, S.cstart, S.grp, S.pos,
+                     S.strm, S.cbox, d_cell_prefix, mode);
   if (tiles) {
     const int tb = (int)std::min<int64_t>(std::max<int64_t>((ncol + 3) / 4, 1), 16384);
     hipLaunchKernelGGL(k_tiles, dim3(tb), dim3(256), 0, st, d_geom, 1, S.cstart, d_maxspan,
@@ -541,7 +533,7 @@ struct Binning {
   Table t32, t64;
   int shift;
   float AB32;
-  float eps32;
+  float eps32, eps32_3;
   Bounds bnd;
   float inv_dpi32, pi_delta, pi_lo32, pi_hi32;
   double dpi;
@@ -578,6 +570,7 @@ static int make_binning(int mode, int prec, const double *edges, int nedges, dou
   if (prec != F32R) B.t32 = B.t64;
   B.AB32 = A32[nb];
   B.eps32 = f32_up(B.bnd.eps);
+  B.eps32_3 = f32_up(B.bnd.eps + 2.0 * std::ldexp(1.0, -24) * EB * 1.01);
   B.C32 = C32;
   B.A32 = A32;
   B.dpi = mode == WP ? pimax / npi : 1.0;
@@ -815,11 +808,13 @@ static int run(const Call &c, uint64_t *npairs, double *wsum, double *ravg) {
     put(d_a32, B.A32.data(), (size_t)c.nedges * 4);
     HIPCHK(hipMemcpyAsync(up0, hup.data(), upn, hipMemcpyHostToDevice, st));
   }
-  hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(256), 0, st, d_hist, (int64_t)nout);
-  hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(256), 0, st, d_hw, (int64_t)nout);
-  hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(256), 0, st, d_hwr, (int64_t)nout);
-  hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, d_stats, (int64_t)6);
-  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, d_err, (int64_t)1, 0);
+  {
+    // histogram, weight sums, statistics and error flag are carved
+    // consecutively: one fill clears them all (zero bits are 0 and 0.0)
+    const int64_t words = (int64_t)(((char *)(d_err + 1) - (char *)d_hist) / 4);
+    hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)std::min<int64_t>((words + 255) / 256, 64)),
+                       dim3(256), 0, st, (int *)d_hist, words, 0);
+  }
 
   // ---- cell build
   rc = launch_build(st, &d_sm->pts[0], &d_sm->geom[0], S1, p1.n, ncell, ncol, c.mode,
@@ -862,6 +857,7 @@ static int run(const Call &c, uint64_t *npairs, double *wsum, double *ravg) {
   P.nslots = nb + 2;
   P.AB32 = B.AB32;
   P.eps32 = B.eps32;
+  P.eps32_3 = B.eps32_3;
   P.EB = B.E[nb];
   P.pimax = c.pimax;
   P.dpi = B.dpi;
@@ -1161,6 +1157,7 @@ static void batch_carve(Carver &cv, cp_plan &pl, Batch &b) {
   b.S.cid = cv.take<int>(std::max<int64_t>(b.npts_tot, 1));
   b.S.rank = cv.take<int>(std::max<int64_t>(b.npts_tot, 1));
   b.S.pos = cv.take<double4>(b.npts_tot + 8);
+  b.S.grp = cv.take<double4>(std::max<int64_t>(b.npts_tot, 1));
   b.S.strm = cv.take<float4>(b.npts_tot + 8);
   b.S.cbox = cv.take<CellBox>(b.ncell_tot);
   b.S.colcnt = cv.take<int>(b.ncol_tot + 1);
@@ -1220,6 +1217,7 @@ static int batch_upload(cp_plan &pl, Batch &b) {
   P.nslots = b.nb + 2;
   P.AB32 = b.B.AB32;
   P.eps32 = b.B.eps32;
+  P.eps32_3 = b.B.eps32_3;
   P.EB = b.B.E[b.nb];
   P.pimax = b.pimax;
   P.dpi = b.B.dpi;
@@ -1255,14 +1253,9 @@ static int batch_enqueue(cp_plan &pl, Batch &b, hipStream_t st) {
   hipLaunchKernelGGL(k_scan_segments, dim3(nm), dim3(1024), 0, st, b.S.ccount, b.S.cstart,
                      b.d_segs);
   hipLaunchKernelGGL(k_group, dim3(blocks(pl.maxn, 256, 4096), nm), dim3(256), 0, st, b.d_pts,
-                     b.d_geom, b.S.cstart, b.S.cid, b.S.rank, (int *)b.S.strm, (double *)b.S.pos);
-  hipLaunchKernelGGL(k_zrank, dim3(blocks(b.ncell_tot, 4, 65536)), dim3(256), 0, st, b.d_geom,
-                     nm, b.S.cstart, (const int *)b.S.strm, (const double *)b.S.pos, b.S.rank,
-                     b.d_cell_prefix);
-  hipLaunchKernelGGL(k_scatter, dim3(blocks(pl.maxn, 256, 4096), nm), dim3(256), 0, st, b.d_pts,
-                     b.d_geom, b.S.cstart, b.S.cid, b.S.rank, b.S.pos, b.S.strm, b.mode);
-  hipLaunchKernelGGL(k_cellbox, dim3(blocks(b.ncell_tot, 4, 65536)), dim3(256), 0, st, b.d_geom,
-                     nm, b.S.cstart, b.S.pos, b.S.cbox, b.d_cell_prefix);
+                     b.d_geom, b.S.cstart, b.S.cid, b.S.rank, b.S.grp);
+  hipLaunchKernelGGL(k_cellfin, dim3(blocks(b.ncell_tot, 4, 65536)), dim3(256), 0, st, b.d_geom,
+                     nm, b.S.cstart, b.S.grp, b.S.pos, b.S.strm, b.S.cbox, b.d_cell_prefix, b.mode);
   const int tb = blocks(b.ncol_tot, 4, 65536);
   hipLaunchKernelGGL(k_tiles, dim3(tb), dim3(256), 0, st, b.d_geom, nm, b.S.cstart, b.d_maxspan,
                      b.d_col_prefix, b.S.colcnt, b.S.coloff, b.S.tiles, 0);

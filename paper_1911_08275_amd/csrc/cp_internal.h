@@ -93,6 +93,8 @@ struct PairParams {
   float AB32;                // binary32 s~ >= AB32 -> certainly >= E_B
   float eps32;               // binary32 bound on |(s~ - E_t) - (s - E_t)| of the
                              // folded two-slot evaluation (rounded up)
+  float eps32_3;             // the same for the three-slot evaluation, whose second
+                             // difference is formed from the first (adds 2 u E_B)
   double EB;                 // E_B
   // wp
   double pimax, dpi;

@@ -180,107 +180,104 @@ __global__ __launch_bounds__(256) void k_assign(const PointsDev *pts, const Grid
   if (bad) atomicOr(err, bad);
 }
 
-// Scatter into cell order: binary64 (x, y, z, w) and the binary32 stream
-// record used by the pair kernels, in the frame of the point's own cell:
-//   xi: (-2 px, -2 py, -2 pz, |p|^2)      wp: (-2 px, -2 py, pz, px^2 + py^2)
-// with p = fl32(x - O_cell) and O_cell the cell centre.
-__global__ __launch_bounds__(256) void k_scatter(const PointsDev *pts, const GridGeom *geom,
-                                                 const int *cstart, const int *cid,
-                                                 const int *rank, double4 *pos,
-                                                 float4 *strm, int mode) {
-  const PointsDev P = pts[blockIdx.y];
-  const GridGeom &G = geom[blockIdx.y];
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < P.n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const int cell = cid[G.pbase + i];
-    const int64_t dst = G.pbase + cstart[G.sbase + cell] + rank[G.pbase + i];
-    double v[3] = {load_coord(P.x, P.dtype, i), load_coord(P.y, P.dtype, i),
-                   load_coord(P.z, P.dtype, i)};
-    double w = P.w ? P.w[i] : 1.0;
-    pos[dst] = make_double4(v[0], v[1], v[2], w);
-    int cz = cell % G.n[2];
-    int cy = (cell / G.n[2]) % G.n[1];
-    int cx = cell / (G.n[2] * G.n[1]);
-    float px = (float)(v[0] - frame_origin(G, 0, cx));
-    float py = (float)(v[1] - frame_origin(G, 1, cy));
-    float pz = (float)(v[2] - frame_origin(G, 2, cz));
-    float4 s;
-    s.x = -2.0f * px;
-    s.y = -2.0f * py;
-    if (mode == XI) {
-      s.z = -2.0f * pz;
-      s.w = __builtin_fmaf(pz, pz, __builtin_fmaf(py, py, px * px));
-    } else {
-      s.z = pz;
-      s.w = __builtin_fmaf(py, py, px * px);
-    }
-    strm[dst] = s;
-  }
-}
-
-// z order inside each cell (ties by input index), so the pair kernel can
-// cut a unit down to the z-window its tile can reach (Section 2.2: late
-// entry and early exit on z-sorted cells).  k_group lists each cell's points
-// in the atomic order together with their z; k_zrank turns every point's rank
-// into its rank in z.  Both use the position and stream buffers as scratch
-// (k_scatter overwrites them).  Cells above kZSortMax points keep the atomic
-// order; the pair kernel searches those whole.
+// Cell order, z ascending inside each cell (Section 2.1 contiguous per-cell
+// storage; Section 2.2 z-sorted cells for late entry / early exit).  k_group
+// copies every point's (x, y, z, w) to its cell's range in the atomic order;
+// k_cellfin, one wave per cell, ranks the cell's points by z (ties by grouped
+// position, so the ranks form a permutation), writes them in that order
+// together with their binary32 stream records, and takes the cell's bounding
+// box.  Cells above kZSortMax points keep the grouped order.
 __global__ __launch_bounds__(256) void k_group(const PointsDev *pts, const GridGeom *geom,
                                                const int *cstart, const int *cid,
-                                               const int *rank, int *idx, double *zs) {
+                                               const int *rank, double4 *grp) {
   const PointsDev P = pts[blockIdx.y];
   const GridGeom &G = geom[blockIdx.y];
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < P.n;
        i += (int64_t)gridDim.x * blockDim.x) {
     const int cell = cid[G.pbase + i];
     const int64_t k = G.pbase + cstart[G.sbase + cell] + rank[G.pbase + i];
-    idx[k] = (int)i;
-    zs[k] = load_coord(P.z, P.dtype, i);
+    grp[k] = make_double4(load_coord(P.x, P.dtype, i), load_coord(P.y, P.dtype, i),
+                          load_coord(P.z, P.dtype, i), P.w ? P.w[i] : 1.0);
   }
 }
 
-// One wave per cell: the cell's z values are staged in the wave's LDS slice,
-// kZChunk at a time, and each lane ranks NP of its points per broadcast scan
-// over them.  Ties in z are broken by the grouped position, which makes the
-// ranks a permutation (counts do not depend on the order inside a cell).
-constexpr int kZChunk = 1024;
+// Stream record of a point in the frame of its own cell (centre O):
+//   xi: (-2 px, -2 py, -2 pz, |p|^2)      wp: (-2 px, -2 py, pz, px^2 + py^2)
+// with p = fl32(x - O).
+__device__ inline float4 stream_record(const GridGeom &G, int cell, const double4 &v, int mode) {
+  const int cz = cell % G.n[2];
+  const int cy = (cell / G.n[2]) % G.n[1];
+  const int cx = cell / (G.n[2] * G.n[1]);
+  const float px = (float)(v.x - frame_origin(G, 0, cx));
+  const float py = (float)(v.y - frame_origin(G, 1, cy));
+  const float pz = (float)(v.z - frame_origin(G, 2, cz));
+  float4 s;
+  s.x = -2.0f * px;
+  s.y = -2.0f * py;
+  if (mode == XI) {
+    s.z = -2.0f * pz;
+    s.w = __builtin_fmaf(pz, pz, __builtin_fmaf(py, py, px * px));
+  } else {
+    s.z = pz;
+    s.w = __builtin_fmaf(py, py, px * px);
+  }
+  return s;
+}
 
+constexpr int kZChunk = 256;    // z values staged in LDS per step, per wave
+
+// NP points per lane: rank by a broadcast scan over the staged z values,
+// then write them (and their stream records) at b + rank; min/max update.
 template <int NP>
-__device__ inline void zrank_pass(const double *zs, const int *idx, int64_t base, int64_t pbase,
-                                  int n, int q0, int lane, double *zw, int *rank) {
-  double zi[NP];
+__device__ inline void cellfin_pass(const GridGeom &G, int cell, const double4 *grp,
+                                    int64_t base, int n, int q0, int lane, double *zw,
+                                    double4 *pos, float4 *strm, int mode, double mn[3],
+                                    double mx[3]) {
+  double4 v[NP];
   int kq[NP], r[NP];
 #pragma unroll
   for (int p = 0; p < NP; p++) {
     kq[p] = q0 + p * 64 + lane;
-    zi[p] = kq[p] < n ? zs[base + kq[p]] : 0.0;
-    r[p] = 0;
+    v[p] = kq[p] < n ? grp[base + kq[p]] : make_double4(0.0, 0.0, 0.0, 0.0);
+    r[p] = kq[p];
   }
-  for (int c0 = 0; c0 < n; c0 += kZChunk) {
-    const int cnt = min(kZChunk, n - c0);
-    if (q0 == 0 || n > kZChunk) {   // (re)stage this chunk
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      for (int t = lane; t < cnt; t += 64) zw[t] = zs[base + c0 + t];
-      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-    }
+  if (n <= kZSortMax) {
+#pragma unroll
+    for (int p = 0; p < NP; p++) r[p] = 0;
+    for (int c0 = 0; c0 < n; c0 += kZChunk) {
+      const int cnt = min(kZChunk, n - c0);
+      if (q0 == 0 || n > kZChunk) {   // (re)stage this chunk
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        for (int t = lane; t < cnt; t += 64) zw[t] = grp[base + c0 + t].z;
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+      }
 #pragma unroll 4
-    for (int t = 0; t < cnt; t++) {
-      const double zj = zw[t];
+      for (int t = 0; t < cnt; t++) {
+        const double zj = zw[t];
 #pragma unroll
-      for (int p = 0; p < NP; p++) r[p] += (zj < zi[p] || (zj == zi[p] && c0 + t < kq[p])) ? 1 : 0;
+        for (int p = 0; p < NP; p++)
+          r[p] += (zj < v[p].z || (zj == v[p].z && c0 + t < kq[p])) ? 1 : 0;
+      }
     }
   }
 #pragma unroll
-  for (int p = 0; p < NP; p++)
-    if (kq[p] < n) rank[pbase + idx[base + kq[p]]] = r[p];
+  for (int p = 0; p < NP; p++) {
+    if (kq[p] < n) {
+      pos[base + r[p]] = v[p];
+      strm[base + r[p]] = stream_record(G, cell, v[p], mode);
+      mn[0] = fmin(mn[0], v[p].x); mx[0] = fmax(mx[0], v[p].x);
+      mn[1] = fmin(mn[1], v[p].y); mx[1] = fmax(mx[1], v[p].y);
+      mn[2] = fmin(mn[2], v[p].z); mx[2] = fmax(mx[2], v[p].z);
+    }
+  }
 }
 
-__global__ __launch_bounds__(256) void k_zrank(const GridGeom *geom, int nmock,
-                                               const int *cstart, const int *idx,
-                                               const double *zs, int *rank,
-                                               const int64_t *cell_prefix) {
+__global__ __launch_bounds__(256) void k_cellfin(const GridGeom *geom, int nmock,
+                                                 const int *cstart, const double4 *grp,
+                                                 double4 *pos, float4 *strm, CellBox *cbox,
+                                                 const int64_t *cell_prefix, int mode) {
   __shared__ double zsh[4][kZChunk];
   const int w = threadIdx.x >> 6;
   const int wid = (int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6);
@@ -297,41 +294,13 @@ __global__ __launch_bounds__(256) void k_zrank(const GridGeom *geom, int nmock,
     const int c = (int)(gc - cell_prefix[lo]);
     const int b = cstart[G.sbase + c], e = cstart[G.sbase + c + 1];
     const int n = e - b;
-    if (n <= 1 || n > kZSortMax) continue;   // one point: rank 0 already
     const int64_t base = G.pbase + b;
+    double mn[3] = {DBL_MAX, DBL_MAX, DBL_MAX}, mx[3] = {-DBL_MAX, -DBL_MAX, -DBL_MAX};
     if (n <= 64) {
-      zrank_pass<1>(zs, idx, base, G.pbase, n, 0, lane, zw, rank);
+      cellfin_pass<1>(G, c, grp, base, n, 0, lane, zw, pos, strm, mode, mn, mx);
     } else {
       for (int q0 = 0; q0 < n; q0 += 4 * 64)
-        zrank_pass<4>(zs, idx, base, G.pbase, n, q0, lane, zw, rank);
-    }
-  }
-}
-
-// Per-cell bounding boxes (binary64), one wave per cell.
-__global__ __launch_bounds__(256) void k_cellbox(const GridGeom *geom, int nmock,
-                                                 const int *cstart, const double4 *pos,
-                                                 CellBox *cbox, const int64_t *cell_prefix) {
-  const int wid = (int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6);
-  const int lane = threadIdx.x & 63;
-  const int64_t total = cell_prefix[nmock];
-  for (int64_t gc = wid; gc < total; gc += (int64_t)gridDim.x * (blockDim.x >> 6)) {
-    // find the catalogue of global cell gc (few catalogues per call, or a
-    // monotone prefix array for batches)
-    int lo = 0, hi = nmock - 1;
-    while (lo < hi) {
-      int mid = (lo + hi + 1) >> 1;
-      if (cell_prefix[mid] <= gc) lo = mid; else hi = mid - 1;
-    }
-    const GridGeom &G = geom[lo];
-    const int c = (int)(gc - cell_prefix[lo]);
-    const int b = cstart[G.sbase + c], e = cstart[G.sbase + c + 1];
-    double mn[3] = {DBL_MAX, DBL_MAX, DBL_MAX}, mx[3] = {-DBL_MAX, -DBL_MAX, -DBL_MAX};
-    for (int k = b + lane; k < e; k += 64) {
-      double4 p = pos[G.pbase + k];
-      mn[0] = fmin(mn[0], p.x); mx[0] = fmax(mx[0], p.x);
-      mn[1] = fmin(mn[1], p.y); mx[1] = fmax(mx[1], p.y);
-      mn[2] = fmin(mn[2], p.z); mx[2] = fmax(mx[2], p.z);
+        cellfin_pass<4>(G, c, grp, base, n, q0, lane, zw, pos, strm, mode, mn, mx);
     }
     for (int off = 32; off > 0; off >>= 1) {
       for (int a = 0; a < 3; a++) {

@@ -439,6 +439,54 @@ __device__ inline void loop_xi_f32_two(const PairParams &P, WaveArea A, const La
   if (U.slot_hi <= nb) atomicAdd(&A.hist[U.slot_hi * 64 + lane], nhi);
 }
 
+// xi, binary32, a unit whose pairs can only land in slot_lo, slot_lo + 1 or
+// slot_lo + 2: edges E_a = E[slot_lo] and E_b = E[slot_lo + 1] decide.
+// d1 = s~ - E_a comes from the folded Gram form as in the two-slot loop and
+// d2 = fl(d1 + fl32(E_a - E_b)) from it in one add; the add keeps the sign of
+// its exact result, so d2's decision error is that of d1 plus u |E_a - E_b|,
+// which eps32_3 covers.  Sign counts give the three slot counts; lanes with
+// a |d| below the bound re-evaluate those pairs in a second pass.
+// exec = valid lanes.
+template <bool SHIFT>
+__device__ inline void loop_xi_f32_three(const PairParams &P, WaveArea A, const LanePt &L,
+                                         int lane, float rx, float ry, float rz, float ra,
+                                         const Unit &U, const double *sE, uint32_t &nrechk) {
+  const int nb = P.nb;
+  const double Ea = sE[U.slot_lo], Eb = sE[U.slot_lo + 1];
+  const float b = (float)((double)ra - Ea);
+  const float c = (float)(Ea - Eb);
+  const float eps = P.eps32_3;
+  uint32_t n1 = 0, n2 = 0;
+  float mn = 3.0e38f;
+  stream_f32(U.strm, U.jb, U.je, [&](int, float qx, float qy, float qz, float qw) {
+    const float d1 = gram3(rx, ry, rz, b, qx, qy, qz, qw);
+    const float d2 = d1 + c;
+    n1 += __float_as_uint(d1) >> 31;
+    n2 += __float_as_uint(d2) >> 31;
+    mn = fminf(mn, fminf(fabsf(d1), fabsf(d2)));
+  });
+  uint32_t u1 = 0, u2 = 0, un = 0;
+  if (mn < eps) {
+    stream_f32(U.strm, U.jb, U.je, [&](int j, float qx, float qy, float qz, float qw) {
+      const float d1 = gram3(rx, ry, rz, b, qx, qy, qz, qw);
+      const float d2 = d1 + c;
+      if (fabsf(d1) < eps || fabsf(d2) < eps) {
+        recheck_xi<SHIFT>(A, L, lane, U, j, sE, nb);
+        u1 += __float_as_uint(d1) >> 31;
+        u2 += __float_as_uint(d2) >> 31;
+        un++;
+      }
+    });
+    nrechk += un;
+  }
+  const uint32_t c0 = n1 - u1;                       // below E_a
+  const uint32_t c1 = (n2 - u2) - c0;                // [E_a, E_b)
+  const uint32_t c2 = (uint32_t)(U.je - U.jb) - un - (n2 - u2);   // at or above E_b
+  if (U.slot_lo >= 1) atomicAdd(&A.hist[U.slot_lo * 64 + lane], c0);
+  atomicAdd(&A.hist[(U.slot_lo + 1) * 64 + lane], c1);
+  if (U.slot_lo + 2 <= nb) atomicAdd(&A.hist[(U.slot_lo + 2) * 64 + lane], c2);
+}
+
 // xi, binary32, general unit: per-lane table lookup.  OWN: one of the tile's
 // own cells (auto-count), only j > i pairs.  Uncertain pairs are counted in
 // the first pass and re-evaluated in a second pass only when a lane has one.
@@ -956,6 +1004,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
               if (valid) {
                 if (shifted) loop_xi_f32_two<true>(P, A, L, lane, rxf, ryf, rzf, ra, U, sE, nrechk);
                 else loop_xi_f32_two<false>(P, A, L, lane, rxf, ryf, rzf, ra, U, sE, nrechk);
+              }
+            } else if (!own && U.slot_hi == U.slot_lo + 2) {
+              if (valid) {
+                if (shifted) loop_xi_f32_three<true>(P, A, L, lane, rxf, ryf, rzf, ra, U, sE, nrechk);
+                else loop_xi_f32_three<false>(P, A, L, lane, rxf, ryf, rzf, ra, U, sE, nrechk);
               }
             } else {
 #define CP_XI(O, SH) loop_xi_f32<O, SH>(P, A, L, lane, rxf, ryf, rzf, ra, U, tab32, sE, nrechk)
