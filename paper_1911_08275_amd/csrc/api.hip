@@ -40,29 +40,6 @@ __global__ void k_tiles(const GridGeom *geom, int nmock, const int *cstart, cons
                         int emit);
 template <int MODE, int PREC, int W> __global__ void k_pairs(PairParams P);
 
-struct LdsLayout {
-  size_t tab32, tab64, E, common, wave_hist, wave_w, wave_bytes;
-};
-static size_t align16h(size_t v) { return (v + 15) & ~(size_t)15; }
-// identical to the device-side layout in pair_kernels.hip
-static LdsLayout lds_layout_host(int mode, int prec, int weighted, int n32, int n64, int nb,
-                                 int npi) {
-  LdsLayout L;
-  size_t off = 0;
-  L.tab32 = off;
-  off += (size_t)(prec == F32R ? n32 : 0) * 8;
-  L.tab64 = off;
-  off += (size_t)n64 * 8;
-  L.E = off;
-  off += (size_t)(nb + 1) * 8;
-  L.common = align16h(off);
-  const int NS = nb + 2;
-  const size_t words = mode == XI ? (size_t)NS * 64 : (size_t)NS * npi;
-  L.wave_hist = align16h(words * 4);
-  L.wave_w = weighted ? (mode == XI ? (size_t)NS * kWStripe : words) * 8 : 0;
-  L.wave_bytes = L.wave_hist + 2 * L.wave_w;
-  return L;
-}
 
 // ------------------------------------------------------------ error state
 
@@ -874,7 +851,7 @@ static int run(const Call &c, uint64_t *npairs, double *wsum, double *ravg) {
   P.stats = d_stats;
   P.hist_stride = nout;
   const int nwaves = 4;
-  const LdsLayout LY = lds_layout_host(c.mode, prec, weighted, n32, n64, nb, npi);
+  const LdsLayout LY = lds_layout(c.mode, prec, weighted, n32, n64, nb, npi);
   const size_t lds = LY.common + nwaves * LY.wave_bytes;
   if (lds > 160 * 1024) return fail(CP_ERR_INVALID_ARG, "too many bins for the LDS budget");
   if ((rc = launch_pairs(st, c.mode, prec, weighted, P, lds, nwaves))) return rc;
@@ -1135,7 +1112,7 @@ static int batch_prepare(cp_plan &pl, Batch &b, int mode, int prec, const double
   b.segs.push_back({0, 0, b.ncol_tot});
   b.maxtiles = max_tiles_bound(b.npts_tot, b.ncell_tot, b.ncol_tot);
   b.nwaves = 4;
-  const LdsLayout LY = lds_layout_host(mode, b.prec, 0, (int)b.B.t32.e.size(),
+  const LdsLayout LY = lds_layout(mode, b.prec, 0, (int)b.B.t32.e.size(),
                                        (int)b.B.t64.e.size(), b.nb, b.npi);
   b.lds = LY.common + b.nwaves * LY.wave_bytes;
   if (b.lds > 160 * 1024) return fail(CP_ERR_INVALID_ARG, "too many bins for the LDS budget");

@@ -728,32 +728,6 @@ __device__ inline void loop_f64(const PairParams &P, WaveArea A, const LanePt &L
 
 // ------------------------------------------------------------------ kernel
 
-__host__ __device__ inline size_t align16(size_t v) { return (v + 15) & ~(size_t)15; }
-
-struct LdsLayout {
-  size_t tab32, tab64, E, common, wave_hist, wave_w, wave_bytes;
-};
-
-__host__ __device__ inline LdsLayout lds_layout(int mode, int prec, int weighted, int n32, int n64,
-                                               int nb, int npi) {
-  LdsLayout L;
-  size_t off = 0;
-  L.tab32 = off;
-  off += (size_t)(prec == F32R ? n32 : 0) * 8;
-  L.tab64 = off;
-  off += (size_t)n64 * 8;
-  L.E = off;
-  off += (size_t)(nb + 1) * 8;
-  L.common = align16(off);
-  const int NS = nb + 2;
-  const size_t words = mode == XI ? (size_t)NS * 64 : (size_t)NS * npi;
-  L.wave_hist = align16(words * 4);
-  // weight sums are shared by the wave (one row of slots), not lane-private
-  L.wave_w = weighted ? (mode == XI ? (size_t)NS * kWStripe : words) * 8 : 0;
-  L.wave_bytes = L.wave_hist + 2 * L.wave_w;
-  return L;
-}
-
 // Weighted xi always runs in binary64 (the host routes it there), so
 // <XI, F32R, 1> is not instantiated.
 template <int MODE, int PREC, int W>
