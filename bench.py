@@ -59,6 +59,35 @@ def time_steps(fn, steps, warmup):
     return dt, stats
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_pairs_xi_weighted_1e6_traffic.md")
+KERNEL_SRC = os.path.join(ROOT, "paper_1911_08275_amd", "csrc", "pair_kernels.hip")
+
+
+def measured_traffic(refine):
+    """HBM bytes per launch of the headline pair kernel from the committed
+    FETCH_SIZE / WRITE_SIZE counter summary, or None when the kernel source
+    or the refine factors differ from those the counters were taken with."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    vals = {}
+    for line in text.splitlines():
+        if line.startswith("- ") and ":" in line:
+            k, v = line[2:].split(":", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    try:
+        src = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+        if vals.get("pair_kernels.hip sha256") != src:
+            return None
+        if vals.get("refine") != ",".join(str(r) for r in refine):
+            return None
+        return int(vals["fetch bytes per launch"]) + int(vals["write bytes per launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def roofline(cand, inrange_unique, ms_pairs, weighted):
     ops = OPS_PER_CANDIDATE * cand + (OPS_PER_INRANGE_WEIGHTED if weighted else OPS_PER_INRANGE) \
         * inrange_unique
@@ -127,6 +156,7 @@ def main():
     ms_pairs64 = float(np.mean([s.stats["ms_pairs"] for s in s64]))
     st = gw.stats
     roof = roofline(st["candidates"], pairs // 2, ms_w, True)
+    roof["traffic"] = measured_traffic(st["refine"])
     roof32 = roofline(g32.stats["candidates"], pairs // 2, ms_pairs32, False)
     roof64 = roofline(g64.stats["candidates"], pairs // 2, ms_pairs64, False)
 
@@ -252,11 +282,12 @@ def main():
         out["extras"] = extras
 
     if args.copy_calib:
-        # plain copy of a known size, for scaling memory counters
+        # a plain copy kernel of known size (reads and writes 256 MiB each), to
+        # scale the FETCH_SIZE / WRITE_SIZE memory counters
         a = torch.empty(256 * 1024 * 1024 // 4, dtype=torch.float32, device="cuda").fill_(1.0)
         b = torch.empty_like(a)
         for _ in range(3):
-            b.copy_(a)
+            torch.mul(a, 1.0, out=b)
         torch.cuda.synchronize()
         out["copy_calib_bytes"] = a.numel() * 4
 

@@ -175,6 +175,37 @@ def test_refine_factors(native, refine):
         _check(g, refw)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_dense_cell_unsorted_path(native, prec):
+    """A cluster of 9000 points inside one cell (more than the 4096 points up
+    to which cells are z-sorted): that cell keeps its grouped order and is
+    searched whole, its neighbours are sorted and cut to z-windows; counts and
+    weighted sums still match the oracle."""
+    rng = np.random.Generator(np.random.PCG64(41))
+    n1, n2 = 9000, 6000
+    c = np.array([200.0, 210.0, 220.0])
+    dense = c + rng.normal(scale=1.2, size=(n1, 3))
+    spread = rng.uniform(150.0, 270.0, (n2, 3))
+    p = np.concatenate([dense, spread], 0) % 420.0
+    w = rng.uniform(0.5, 1.5, len(p))
+    cat = synth.Catalog(*(np.ascontiguousarray(p[:, a]) for a in range(3)), w=w)
+    edges = synth.log_edges(0.1, 25.0, 14)
+    _say("dense cell", prec)
+    ref = oracle.xi(cat, edges, periodic=True, box=420.0)
+    d = native.to_device(cat)
+    for refine in [(1, 1, 1), (2, 2, 2)]:
+        g = native.countpairs_xi(d, edges, precision=prec, periodic=True, boxsize=420.0,
+                                 refine=refine, need_ravg=True)
+        _check(g, ref, weighted=True)
+        g = native.countpairs_xi(d, edges, precision=prec, periodic=True, boxsize=420.0,
+                                 refine=refine)
+        _check(g, ref)
+    refw = oracle.wp(cat, edges, 40.0, 40, periodic=True, box=420.0)
+    g = native.countpairs_wp(d, edges, 40.0, 40, precision=prec, periodic=True, boxsize=420.0,
+                             refine=(1, 1, 1))
+    _check(g, refw)
+
+
 def test_unique_mode_and_pruning_stats(native):
     cat = synth.clustered(30_000, 600, 1.5, 420.0, seed=6)
     edges = synth.log_edges(0.1, 25.0, 14)
