@@ -701,7 +701,7 @@ static int run(const Call &c, uint64_t *npairs, double *wsum, double *ravg) {
   float *d_c32 = nullptr, *d_a32 = nullptr;
   auto layout = [&](Carver &cv, SetBufs &S1, SetBufs &S2, Smalls *&sm, uint2 *&t32, uint2 *&t64,
                     double *&E, unsigned long long *&hist, double *&hw, double *&hwr,
-                    unsigned long long *&stats, unsigned long long *&qhead, int *&err) {
+                    unsigned long long *&stats, int *&err) {
     float *&c32 = d_c32, *&a32 = d_a32;
     carve_set(cv, S1, p1.n, ncell, ncol, true, maxt);
     if (!autoc) carve_set(cv, S2, p2.n, ncell, ncol, false, 0);
@@ -714,19 +714,18 @@ static int run(const Call &c, uint64_t *npairs, double *wsum, double *ravg) {
     hist = cv.take<unsigned long long>(nout);
     hw = cv.take<double>(nout);
     hwr = cv.take<double>(nout);
-    stats = cv.take<unsigned long long>(6);   // 4 counters, queue head, tile count
-    qhead = stats + 4;
+    stats = cv.take<unsigned long long>(kStatWords);
     err = cv.take<int>(1);
   };
   SetBufs S1, S2;
   Smalls *d_sm;
   uint2 *d_t32, *d_t64;
   double *d_E, *d_hw, *d_hwr;
-  unsigned long long *d_hist, *d_stats, *d_qhead;
+  unsigned long long *d_hist, *d_stats;
   int *d_err;
   {
     Carver dry(nullptr, true);
-    layout(dry, S1, S2, d_sm, d_t32, d_t64, d_E, d_hist, d_hw, d_hwr, d_stats, d_qhead, d_err);
+    layout(dry, S1, S2, d_sm, d_t32, d_t64, d_E, d_hist, d_hw, d_hwr, d_stats, d_err);
     const size_t need = dry.off + 256;
     void *base;
     if (o.workspace) {
@@ -751,7 +750,7 @@ static int run(const Call &c, uint64_t *npairs, double *wsum, double *ravg) {
       base = g_arena.base;
     }
     Carver cv(base, false);
-    layout(cv, S1, S2, d_sm, d_t32, d_t64, d_E, d_hist, d_hw, d_hwr, d_stats, d_qhead, d_err);
+    layout(cv, S1, S2, d_sm, d_t32, d_t64, d_E, d_hist, d_hw, d_hwr, d_stats, d_err);
   }
   if (autoc) S2 = S1;
 
@@ -811,7 +810,6 @@ static int run(const Call &c, uint64_t *npairs, double *wsum, double *ravg) {
   memset(&P, 0, sizeof(P));
   P.tiles = S1.tiles;
   P.ntiles = S1.coloff + ncol;
-  P.qhead = d_qhead;
   P.nsplit = 2 * g.r[0] + 1;
   P.geom1 = &d_sm->geom[0];
   P.geom2 = &d_sm->geom[1];
@@ -861,7 +859,7 @@ static int run(const Call &c, uint64_t *npairs, double *wsum, double *ravg) {
   // carved consecutively, so one download brings them all
   std::vector<unsigned long long> h(nout);
   std::vector<double> hwv(nout), hwrv(nout);
-  unsigned long long hst[6];
+  unsigned long long hst[kStatWords];
   int eflag = 0;
   char *dn0 = (char *)d_hist;
   const size_t dnn = (size_t)((char *)(d_err + 1) - dn0);
@@ -879,10 +877,16 @@ static int run(const Call &c, uint64_t *npairs, double *wsum, double *ravg) {
   }
   get(hst, d_stats, sizeof(hst));
   get(&eflag, d_err, sizeof(int));
-  const int ntiles = (int)hst[5];
+  const int ntiles = (int)hst[4];
   if ((rc = map_err_flags(eflag))) return rc;
-  if (hst[4] < (unsigned long long)ntiles * (unsigned long long)P.nsplit)
-    return fail(CP_ERR_INTERNAL, "work queue not drained");
+  {
+    const int64_t nitems = (int64_t)ntiles * P.nsplit;
+    for (int k = 0; k < kQueues; k++) {
+      const int64_t len = nitems * (k + 1) / kQueues - nitems * k / kQueues;
+      if (hst[5 + k] < (unsigned long long)len)
+        return fail(CP_ERR_INTERNAL, "work queue not drained");
+    }
+  }
 
   const double mult = (autoc && o.count_mode == CP_ORDERED) ? 2.0 : 1.0;
   for (int k = 0; k < nout; k++) {
@@ -1016,7 +1020,7 @@ extern "C" size_t countpairs_workspace_size(int kind, int64_t n1, int64_t n2, co
   cv.take<unsigned long long>(nout);
   cv.take<double>(nout);
   cv.take<double>(nout);
-  cv.take<unsigned long long>(6);
+  cv.take<unsigned long long>(kStatWords);
   cv.take<int>(1);
   return cv.off + 256;
 }
@@ -1148,7 +1152,7 @@ static void batch_carve(Carver &cv, cp_plan &pl, Batch &b) {
   b.d_hist = cv.take<unsigned long long>((int64_t)b.nout * nm);
   b.d_hw = cv.take<double>(1);
   b.d_hwr = cv.take<double>(1);
-  b.d_stats = cv.take<unsigned long long>(6);   // 4 counters, queue head, tile count
+  b.d_stats = cv.take<unsigned long long>(kStatWords);
   b.d_err = cv.take<int>(1);
 }
 
@@ -1171,7 +1175,6 @@ static int batch_upload(cp_plan &pl, Batch &b) {
   memset(&P, 0, sizeof(P));
   P.tiles = b.S.tiles;
   P.ntiles = b.S.coloff + b.ncol_tot;
-  P.qhead = b.d_stats + 4;
   P.nsplit = 2 * b.g.r[0] + 1;
   P.geom1 = b.d_geom;
   P.geom2 = b.d_geom;
@@ -1223,7 +1226,7 @@ static int batch_enqueue(cp_plan &pl, Batch &b, hipStream_t st) {
                      b.S.ccount, b.ncell_tot, 0);
   hipLaunchKernelGGL(k_fill_u64, dim3(blocks((int64_t)b.nout * nm, 256, 1024)), dim3(256), 0, st,
                      b.d_hist, (int64_t)b.nout * nm);
-  hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, b.d_stats, (int64_t)6);
+  hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, b.d_stats, (int64_t)kStatWords);
   hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, b.d_err, (int64_t)1, 0);
   hipLaunchKernelGGL(k_assign, dim3(blocks(pl.maxn, 256, 4096), nm), dim3(256), 0, st, b.d_pts,
                      b.d_geom, b.S.ccount, b.S.cid, b.S.rank, b.d_err);
@@ -1427,7 +1430,7 @@ int cp_plan_stats(cp_plan *pl, cp_stats *xs, cp_stats *ws) {
     if (!o) continue;
     memset(o, 0, sizeof(*o));
     if (!b.on) continue;
-    unsigned long long st[5];
+    unsigned long long st[kStatWords];
     int nt = 0;
     HIPCHK(hipMemcpy(st, b.d_stats, sizeof(st), hipMemcpyDeviceToHost));
     HIPCHK(hipMemcpy(&nt, b.S.coloff + b.ncol_tot, sizeof(int), hipMemcpyDeviceToHost));

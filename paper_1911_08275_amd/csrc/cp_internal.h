@@ -13,6 +13,15 @@ constexpr int kMaxBins = 60;        // separation bins; slots 0 and nb+1 are tra
                                     // slot + 1 must fit the 6-bit table code
 constexpr int kMaxPiBins = 256;
 constexpr int kZSortMax = 4096;   // cells up to this many points are z-sorted
+// Work queues of the pair kernel: one per XCD (workgroups are dealt to the
+// MI355X's 8 XCDs round-robin, so blockIdx.x % 8 names the XCD), each
+// holding a contiguous, hence spatially compact, share of the items; a wave
+// drains its own queue first, so a cell's records are reused from its XCD's
+// L2, then helps the others.
+constexpr int kQueues = 8;
+// Statistics words: candidates, rechecks, cell pairs, pruned, tile count,
+// then the kQueues queue heads.
+constexpr int kStatWords = 5 + kQueues;
 constexpr int kWStripe = 8;       // copies of each weight sum per wave (lane & 7)
 
 enum Mode { XI = 0, WP = 1 };
@@ -69,7 +78,6 @@ struct PairParams {
   // work queue
   const Tile *tiles;
   const int *ntiles;         // device: number of tiles in the queue
-  unsigned long long *qhead;
   int nsplit;                // queue items per tile: one per x offset of the
                              // neighbour search (2 r_x + 1 slabs)
   // geometry (indexed by tile.mock); set 2 is the searched (streamed) set
@@ -107,8 +115,8 @@ struct PairParams {
   unsigned long long *hist;  // [nmock][nb * npi]
   double *hw;                // [nmock][nb * npi] sum of weights
   double *hwr;               // [nmock][nb * npi] sum of weight * separation
-  unsigned long long *stats; // candidates, rechecks, cell pairs, pruned, queue head,
-                             // tile count (written by the pair kernel)
+  unsigned long long *stats; // kStatWords: candidates, rechecks, cell pairs, pruned,
+                             // tile count (written by the pair kernel), queue heads
   int hist_stride;           // nb * npi
 };
 

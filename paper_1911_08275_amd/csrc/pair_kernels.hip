@@ -765,16 +765,30 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
   const int64_t nsplit = P.nsplit;
   const int64_t ntiles = *P.ntiles;
   const int64_t nitems = ntiles * nsplit;
-  if (blockIdx.x == 0 && threadIdx.x == 0) P.stats[5] = (unsigned long long)ntiles;
+  if (blockIdx.x == 0 && threadIdx.x == 0) P.stats[4] = (unsigned long long)ntiles;
+  unsigned long long *heads = P.stats + 5;
+  const int home = (int)(blockIdx.x % kQueues);
+  int victim = 0;   // queues found empty so far, counted from the home queue
   int cur_mock = -1;
   unsigned long long since_flush = 0;
   const unsigned long long flush_limit = MODE == XI ? (1ull << 30) : (1ull << 24);
 
   for (;;) {
-    int64_t tix = 0;
-    if (lane == 0) tix = (int64_t)atomicAdd(P.qhead, 1ull);
+    int64_t tix = -1;
+    if (lane == 0) {
+      while (victim < kQueues) {
+        const int k = (home + victim) % kQueues;
+        const int64_t qb = nitems * k / kQueues, qe = nitems * (k + 1) / kQueues;
+        const int64_t i = (int64_t)atomicAdd(&heads[k], 1ull);
+        if (qb + i < qe) {
+          tix = qb + i;
+          break;
+        }
+        victim++;
+      }
+    }
     tix = uni64(__shfl(tix, 0));
-    if (tix >= nitems) break;
+    if (tix < 0) break;
     // item = (tile, x offset of the neighbour search): consecutive items
     // share a tile, so its slabs run on different waves at the same time
     const int64_t tile_ix = tix / nsplit;
