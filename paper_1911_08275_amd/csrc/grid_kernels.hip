@@ -357,8 +357,21 @@ __device__ inline void walk_column(const GridGeom &G, const int *cs, int col, in
   }
 }
 
+// Queue position of a column: blocks of 4 x 4 columns, block rows along x,
+// so the tiles the waves of one XCD work on at the same time (a contiguous
+// stretch of its share of the queue) sit in a compact patch of columns and
+// share their neighbour cells in that XCD's L2.  A bijection on the columns.
+__device__ inline int column_rank(int col, int nx, int ny) {
+  constexpr int B = 4;
+  const int cx = col / ny, cy = col % ny;
+  const int bx = cx / B, by = cy / B;
+  const int w = min(B, nx - bx * B), h = min(B, ny - by * B);
+  return bx * B * ny + by * B * w + (cx - bx * B) * h + (cy - by * B);
+}
+
 // One wave per column: the column's cell starts are staged in the wave's LDS
-// slice, then one lane walks them.
+// slice, then one lane walks them.  Counts and offsets are indexed by the
+// column's queue position.
 __global__ __launch_bounds__(256) void k_tiles(const GridGeom *geom, int nmock,
                                                const int *cstart, const int *maxspan,
                                                const int64_t *col_prefix, int *colcnt,
@@ -383,9 +396,10 @@ __global__ __launch_bounds__(256) void k_tiles(const GridGeom *geom, int nmock,
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
     if (lane == 0) {
-      int64_t n = emit ? coloff[gcol] : 0;
+      const int64_t q = col_prefix[lo] + column_rank(col, G.n[0], G.n[1]);
+      int64_t n = emit ? coloff[q] : 0;
       walk_column(G, cs, col, maxspan[lo], lo, emit, tiles, n);
-      if (!emit) colcnt[gcol] = (int)n;
+      if (!emit) colcnt[q] = (int)n;
     }
   }
 }
