@@ -98,6 +98,138 @@ def roofline(cand, inrange_unique, ms_pairs, weighted):
             "kernel": "k_pairs (pair kernel)", "ops_per_launch": int(ops)}
 
 
+def _median_call(fn, steps):
+    """Median device time of the whole call (ms_total) and the last result."""
+    fn()
+    res = [fn() for _ in range(steps)]
+    return float(np.median([r.stats["ms_total"] for r in res])), res[-1]
+
+
+def sweep_refine(native, steps):
+    """Refine factors and bounding-box pruning on the headline catalogue
+    (the paper's refine-factor and pruning experiments of Section 3.1, on
+    the MI355X): device time of one call per refine (r_x, r_y, r_z), pruning
+    on and off, for weighted binary64 xi and unweighted binary32+recheck xi.
+    Every configuration must give identical counts."""
+    c2 = synth.config2()
+    d2 = native.to_device(c2["cat"])
+    e2 = c2["edges"]
+    log("c2 generated, n =", c2["cat"].n)
+    ref = None
+    rows = []
+    grid = [(rx, ry, rz) for rz in (1, 2, 3) for rx in (1, 2, 3) for ry in (1, 2, 3)]
+    for refine in grid:
+        row = {"refine": list(refine)}
+        for label, prec, w in (("w64", "fp64", True), ("u32", "fp32", False)):
+            for prune in (True, False):
+                ms, g = _median_call(lambda: native.countpairs_xi(
+                    d2, e2, precision=prec, periodic=True, boxsize=420.0, need_ravg=w,
+                    refine=refine, no_prune=not prune), steps)
+                if ref is None:
+                    ref = g.npairs.copy()
+                same = bool((g.npairs == ref).all())
+                key = f"{label}_{'prune' if prune else 'noprune'}"
+                row[key] = {"ms": round(ms, 4), "candidates": g.stats["candidates"],
+                            "units": g.stats["cell_pairs"],
+                            "pruned": g.stats["cell_pairs_pruned"], "same_counts": same}
+        log(json.dumps(row))
+        rows.append(row)
+    auto = {}
+    for label, prec, w in (("w64", "fp64", True), ("u32", "fp32", False)):
+        g = native.countpairs_xi(d2, e2, precision=prec, periodic=True, boxsize=420.0,
+                                 need_ravg=w, refine="auto")
+        auto[label] = g.stats["refine"]
+    all_same = all(r[k]["same_counts"] for r in rows for k in r if k != "refine")
+    print("| refine | w64 pruned ms | w64 unpruned ms | u32 pruned ms | u32 unpruned ms | "
+          "candidates pruned / unpruned (u32) | units skipped |")
+    print("|---|---|---|---|---|---|---|")
+    for r in rows:
+        print(f"| {tuple(r['refine'])} | {r['w64_prune']['ms']:.3f} | {r['w64_noprune']['ms']:.3f} "
+              f"| {r['u32_prune']['ms']:.3f} | {r['u32_noprune']['ms']:.3f} | "
+              f"{r['u32_prune']['candidates'] / 1e9:.2f}e9 / "
+              f"{r['u32_noprune']['candidates'] / 1e9:.2f}e9 | {r['u32_prune']['pruned']} |")
+    print(json.dumps({"sweep": "refine", "rows": rows, "autotuned": auto,
+                      "counts_identical": all_same}), flush=True)
+
+
+def sweep_rmax(native, steps):
+    """R_max scaling (the paper's Section 3.2 experiment, on the MI355X): xi
+    with 14 log bins over [0.1, R] and wp with pi_max = R, 1-wide pi bins, on
+    the headline catalogue, binary64 and binary32+recheck, refine from the
+    autotuner; the CPU oracle is timed on a random sample of primaries against
+    the whole catalogue, and the GPU cross count of that sample must equal it."""
+    import oracle
+    c2 = synth.config2()
+    cat = c2["cat"]
+    d2 = native.to_device(cat)
+    log("c2 generated, n =", cat.n)
+    rng = np.random.Generator(np.random.PCG64(77))
+    rows = []
+    for R in (10.0, 20.0, 40.0, 80.0, 100.0):
+        edges = synth.log_edges(0.1, R, 14)
+        npi = int(R)
+        row = {"rmax": R}
+        for stat in ("xi", "wp"):
+            def call(prec, refine="auto", d=d2):
+                if stat == "xi":
+                    return native.countpairs_xi(d, edges, precision=prec, periodic=True,
+                                                boxsize=420.0, refine=refine)
+                return native.countpairs_wp(d, edges, R, npi, precision=prec, periodic=True,
+                                            boxsize=420.0, refine=refine)
+            res = {}
+            for prec in ("fp64", "fp32"):
+                ms, g = _median_call(lambda: call(prec), steps)
+                res[prec] = (ms, g)
+            pairs = int(res["fp64"][1].npairs.sum())
+            # oracle on a sample of primaries sized for about a second of CPU work
+            per = max(1.0, pairs / cat.n)
+            nprim = int(min(cat.n, max(2000, 3e8 / per)))
+            idx = np.sort(rng.choice(cat.n, nprim, replace=False))
+            sub = cat.subset(idx)
+            t = time.perf_counter()
+            if stat == "xi":
+                ref = oracle.xi(sub, edges, periodic=True, box=420.0, other=cat)
+            else:
+                ref = oracle.wp(sub, edges, R, npi, periodic=True, box=420.0, other=cat)
+            tcpu = time.perf_counter() - t
+            if stat == "xi":
+                gs = native.countpairs_cross(native.to_device(sub), d2, edges, periodic=True,
+                                             boxsize=420.0)
+            else:
+                gs = native.countpairs_cross_wp(native.to_device(sub), d2, edges, R, npi,
+                                                periodic=True, boxsize=420.0)
+            row[stat] = {
+                "pairs": pairs,
+                "fp64_ms": round(res["fp64"][0], 4), "fp32_ms": round(res["fp32"][0], 4),
+                "refine_fp64": res["fp64"][1].stats["refine"],
+                "refine_fp32": res["fp32"][1].stats["refine"],
+                "fp64_pairs_per_s": pairs / (res["fp64"][0] * 1e-3),
+                "fp32_pairs_per_s": pairs / (res["fp32"][0] * 1e-3),
+                "candidates_fp32": res["fp32"][1].stats["candidates"],
+                "recheck_fraction": res["fp32"][1].stats["rechecks"] / max(1, pairs // 2),
+                "counts_equal_fp32_fp64": bool((res["fp64"][1].npairs ==
+                                                res["fp32"][1].npairs).all()),
+                "oracle_pairs_per_s": float(ref.npairs.sum()) / tcpu,
+                "oracle_sample": f"{nprim} primaries, {tcpu:.2f} s",
+                "gpu_matches_oracle_on_sample": bool(
+                    (gs.npairs.reshape(ref.npairs.shape) == ref.npairs).all())}
+        log(json.dumps(row))
+        rows.append(row)
+    print("| R_max | stat | in-range pairs | fp64 ms | fp32 ms | fp32 pairs/s | refine (fp32) | "
+          "oracle pairs/s (sample) | GPU fp32 / oracle | exact |")
+    print("|---|---|---|---|---|---|---|---|---|---|")
+    for r in rows:
+        for stat in ("xi", "wp"):
+            v = r[stat]
+            ok = v["counts_equal_fp32_fp64"] and v["gpu_matches_oracle_on_sample"]
+            print(f"| {r['rmax']:g} | {stat} | {v['pairs']:.3e} | {v['fp64_ms']:.3f} | "
+                  f"{v['fp32_ms']:.3f} | {v['fp32_pairs_per_s']:.3e} | "
+                  f"{tuple(v['refine_fp32'])} | {v['oracle_pairs_per_s']:.3e} | "
+                  f"{v['fp32_pairs_per_s'] / v['oracle_pairs_per_s']:.0f} | {ok} |")
+    print(json.dumps({"sweep": "rmax", "rows": rows, "oracle_threads": oracle.num_threads()}),
+          flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -109,6 +241,9 @@ def main():
     ap.add_argument("--refine", type=str, default=None, help="e.g. 2,2,1")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain device copy of known size (counter calibration)")
+    ap.add_argument("--sweep", choices=("refine", "rmax"), default=None,
+                    help="instead of the benchmark: refine/pruning sweep or R_max scaling "
+                         "sweep (markdown table and one JSON line on stdout)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the pair counts "
@@ -122,6 +257,12 @@ def main():
         sys.exit(1)
     from paper_1911_08275_amd import native
     native.lib()  # fails loudly when the HIP library is missing
+    if args.sweep == "refine":
+        sweep_refine(native, max(3, args.steps // 3))
+        return
+    if args.sweep == "rmax":
+        sweep_rmax(native, max(3, args.steps // 3))
+        return
     refine = tuple(int(v) for v in args.refine.split(",")) if args.refine else None
     # refine factors: given, or picked by the autotuner on first use (during
     # warm-up, outside the timed steps)

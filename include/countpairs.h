@@ -93,6 +93,11 @@ typedef struct {
   void *stream;           /* hipStream_t; NULL = null stream */
   void *workspace;        /* optional device scratch owned by the caller */
   size_t workspace_bytes; /* its size; too small -> CP_ERR_NOMEM */
+  int no_prune;           /* 1: switch off the bounding-box tests of Section 2.2
+                             (no cell pair is skipped, no z-window, no whole-unit
+                             count): every pair of every cell within the refine
+                             reach is evaluated.  For ablations and for checking
+                             that pruning is exact; 0 (default) prunes. */
 } cp_options;
 
 /* Diagnostics of the last successful call on the calling thread. */

@@ -409,6 +409,7 @@ static int check_common(const Call &c) {
     return fail(CP_ERR_INVALID_ARG, "bad precision");
   if (o.count_mode != CP_ORDERED && o.count_mode != CP_UNIQUE)
     return fail(CP_ERR_INVALID_ARG, "bad count_mode");
+  if (o.no_prune != 0 && o.no_prune != 1) return fail(CP_ERR_INVALID_ARG, "no_prune must be 0 or 1");
   if (o.periodic && (!(o.boxsize > 0) || !std::isfinite(o.boxsize)))
     return fail(CP_ERR_INVALID_ARG, "periodic needs a positive finite boxsize");
   for (int a = 0; a < 3; a++)
@@ -843,6 +844,7 @@ static int run(const Call &c, uint64_t *npairs, double *wsum, double *ravg) {
   P.pi_hi32 = B.pi_hi32;
   P.autocorr = autoc ? 1 : 0;
   P.weighted = weighted ? 1 : 0;
+  P.noprune = o.no_prune;
   P.hist = d_hist;
   P.hw = d_hw;
   P.hwr = d_hwr;
@@ -1069,6 +1071,7 @@ struct cp_plan {
   std::vector<cp::PointsDev> pts;
   cp::Batch xi, wp;
   int count_mode = CP_ORDERED;
+  int noprune = 0;
   void *mem = nullptr;
   hipStream_t cap = nullptr;
   hipGraphExec_t gexec = nullptr;
@@ -1208,6 +1211,7 @@ static int batch_upload(cp_plan &pl, Batch &b) {
   P.pi_hi32 = b.B.pi_hi32;
   P.autocorr = 1;
   P.weighted = 0;
+  P.noprune = pl.noprune;
   P.hist = b.d_hist;
   P.hw = b.d_hw;
   P.hwr = b.d_hwr;
@@ -1301,6 +1305,7 @@ int cp_plan_create(const cp_points *mocks, int nmocks, const double *xi_edges, i
     cp_plan *pl = new cp_plan();
     pl->nmock = nmocks;
     pl->count_mode = o->count_mode;
+    pl->noprune = o->no_prune;
     pl->order.resize(nmocks);
     for (int m = 0; m < nmocks; m++) pl->order[m] = m;
     // longest first: the queue hands out the biggest catalogues' tiles first

@@ -111,6 +111,7 @@ struct PairParams {
   // flags
   int autocorr;
   int weighted;
+  int noprune;               // 1: no unit is skipped or narrowed by its bounding box
   // outputs (per catalogue)
   unsigned long long *hist;  // [nmock][nb * npi]
   double *hw;                // [nmock][nb * npi] sum of weights

@@ -894,7 +894,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
             bool far;
             if (MODE == XI) far = (rp + m[2] * m[2]) >= P.EB;
             else far = (rp >= P.EB) || (m[2] >= P.pimax);
-            if (far) {
+            if (far && !P.noprune) {
               ok = false;
               pruned = 1;
             } else {
@@ -908,7 +908,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
               // |dz| <= hz, so only the cell's z-sorted points in
               // [zmin_tile - S - hz, zmax_tile - S + hz] can pair; the slack
               // terms cover binary64 rounding many times over.
-              if (!anywrap && e - b <= kZSortMax) {
+              if (!P.noprune && !anywrap && e - b <= kZSortMax) {
                 // (binary32 square root with a 1e-5 relative allowance: the
                 // window needs no more precision and stays free of binary64
                 // FMAs)
@@ -972,7 +972,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
           since_flush = nj;
         }
         // all pairs of the unit in one bin: count them without separations
-        if (MODE == XI && !W && !own && !anywrap && U.slot_lo == U.slot_hi) {
+        if (MODE == XI && !W && !own && !anywrap && !P.noprune && U.slot_lo == U.slot_hi) {
           if (U.slot_lo >= 1 && U.slot_lo <= P.nb && valid)
             atomicAdd(&A.hist[U.slot_lo * 64 + lane], (uint32_t)nj);
           continue;

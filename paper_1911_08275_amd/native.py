@@ -43,7 +43,7 @@ class cp_options(ctypes.Structure):
                 ("boxsize", ctypes.c_double), ("refine", ctypes.c_int * 3),
                 ("need_ravg", ctypes.c_int), ("count_mode", ctypes.c_int),
                 ("stream", ctypes.c_void_p), ("workspace", ctypes.c_void_p),
-                ("workspace_bytes", ctypes.c_size_t)]
+                ("workspace_bytes", ctypes.c_size_t), ("no_prune", ctypes.c_int)]
 
 
 class cp_stats(ctypes.Structure):
@@ -164,7 +164,8 @@ def to_device(cat, device="cuda", weights: bool = True) -> DevicePoints:
 
 def options(precision: str = "fp32", periodic: bool = False, boxsize: float = 0.0,
             refine: Optional[Sequence[int]] = None, need_ravg: bool = False,
-            count_mode: str = "ordered", stream=None, workspace=None) -> cp_options:
+            count_mode: str = "ordered", stream=None, workspace=None,
+            no_prune: bool = False) -> cp_options:
     o = cp_options()
     lib().cp_default_options(ctypes.byref(o))
     o.precision = {"fp32": CP_PREC_FP32_RECHECK, "fp64": CP_PREC_FP64}[precision]
@@ -175,6 +176,7 @@ def options(precision: str = "fp32", periodic: bool = False, boxsize: float = 0.
             o.refine[a] = int(refine[a])
     o.need_ravg = 1 if need_ravg else 0
     o.count_mode = {"ordered": CP_ORDERED, "unique": CP_UNIQUE}[count_mode]
+    o.no_prune = 1 if no_prune else 0
     if workspace is not None:
         # a caller-owned device buffer (e.g. a torch uint8 tensor)
         o.workspace = ctypes.c_void_p(workspace.data_ptr())

@@ -38,7 +38,20 @@ def test_struct_layouts(native):
     # cp_points: int64 n, 4 pointers, int dtype (padded)
     assert ctypes.sizeof(native.cp_points) == 48
     assert native.cp_options.stream.offset == 40
-    assert ctypes.sizeof(native.cp_options) == 64
+    assert native.cp_options.no_prune.offset == 64
+    assert ctypes.sizeof(native.cp_options) == 72
+
+
+def test_rejects_bad_prune_flag(native):
+    o = native.options()
+    o.no_prune = 2
+    p = native.cp_points(4, 0x1000, 0x2000, 0x3000, 0, native.CP_F64)
+    e = np.asarray((0.1, 1.0, 2.0), dtype=np.float64)
+    out = np.zeros(2, dtype=np.uint64)
+    rc = native.lib().countpairs_xi(ctypes.byref(p), native._dp(e), e.size, ctypes.byref(o),
+                                    native._up(out), None, None)
+    assert rc == -1   # CP_ERR_INVALID_ARG
+    assert "no_prune" in native.lib().countpairs_last_error().decode()
 
 
 def _call_xi(native, n=4, edges=(0.1, 1.0, 2.0), **kw):

@@ -175,6 +175,29 @@ def test_refine_factors(native, refine):
         _check(g, refw)
 
 
+@pytest.mark.parametrize("rmax", [80.0, 100.0])
+def test_large_rmax(native, rmax):
+    """R_max of 80 and 100 in a box of 420 (the top of the paper's R_max
+    scaling range): 5 or 4 cells per axis at refine 1, so the neighbour reach
+    of a cell wraps most of the periodic box; w_p with pi_max = R_max and
+    1-wide pi bins."""
+    cat = synth.clustered(20_000, 400, 1.5, 420.0, seed=31)
+    edges = synth.log_edges(0.1, rmax, 14)
+    npi = int(rmax)
+    ref = oracle.xi(cat, edges, periodic=True, box=420.0)
+    refw = oracle.wp(cat, edges, rmax, npi, periodic=True, box=420.0)
+    d = native.to_device(cat)
+    for refine in ((1, 1, 1), (2, 2, 2), (3, 3, 1)):
+        for prec in ("fp64", "fp32"):
+            _say("large rmax", rmax, refine, prec)
+            g = native.countpairs_xi(d, edges, precision=prec, periodic=True, boxsize=420.0,
+                                     refine=refine)
+            _check(g, ref)
+            g = native.countpairs_wp(d, edges, rmax, npi, precision=prec, periodic=True,
+                                     boxsize=420.0, refine=refine)
+            _check(g, refw)
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_dense_cell_unsorted_path(native, prec):
     """A cluster of 9000 points inside one cell (more than the 4096 points up
@@ -215,6 +238,44 @@ def test_unique_mode_and_pruning_stats(native):
     u = native.countpairs_xi(d, edges, periodic=True, boxsize=420.0, count_mode="unique")
     assert (o.npairs == 2 * u.npairs).all()
     assert o.stats["cell_pairs_pruned"] > 0
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_pruning_off_equals_on(native, prec):
+    """The bounding-box tests of Section 2.2 (unit skipping, z-window, whole-unit
+    counts) only leave out pairs that cannot be in range: with them switched
+    off every count is unchanged and still equals the oracle."""
+    cat = synth.clustered(40_000, 800, 1.5, 420.0, seed=12, weights=True)
+    edges = synth.log_edges(0.1, 25.0, 14)
+    d = native.to_device(cat)
+    ref = oracle.xi(cat, edges, periodic=True, box=420.0)
+    for refine in ((2, 2, 3), (1, 1, 1), (3, 3, 1)):
+        _say("prune on/off xi", prec, refine)
+        kw = dict(precision=prec, periodic=True, boxsize=420.0, refine=refine)
+        on = native.countpairs_xi(d, edges, need_ravg=True, **kw)
+        off = native.countpairs_xi(d, edges, need_ravg=True, no_prune=True, **kw)
+        _check(on, ref, weighted=True)
+        _check(off, ref, weighted=True)
+        assert on.stats["cell_pairs_pruned"] > 0
+        assert off.stats["cell_pairs_pruned"] == 0
+        assert off.stats["candidates"] > on.stats["candidates"]
+        u_on = native.countpairs_xi(d, edges, **kw)
+        u_off = native.countpairs_xi(d, edges, no_prune=True, **kw)
+        _check(u_on, ref)
+        _check(u_off, ref)
+    _say("prune on/off wp", prec)
+    refw = oracle.wp(cat, edges, 40.0, 40, periodic=True, box=420.0)
+    for flag in (False, True):
+        g = native.countpairs_wp(d, edges, 40.0, 40, precision=prec, periodic=True,
+                                 boxsize=420.0, no_prune=flag)
+        _check(g, refw)
+    _say("prune on/off cross", prec)
+    rcat = synth.uniform(60_000, 420.0, seed=13)
+    refc = oracle.xi(cat, edges, periodic=False, other=rcat)
+    dr = native.to_device(rcat)
+    for flag in (False, True):
+        g = native.countpairs_cross(d, dr, edges, precision=prec, periodic=False, no_prune=flag)
+        _check(g, refc)
 
 
 def test_tiny_inputs(native):
