@@ -196,6 +196,40 @@ int cp_plan_results(cp_plan *plan, uint64_t *xi_npairs, uint64_t *wp_npairs);
 int cp_plan_stats(cp_plan *plan, cp_stats *xi_stats, cp_stats *wp_stats);
 int cp_plan_destroy(cp_plan *plan);
 
+/*
+ * Estimators on top of the counts (Section 1).  Host functions on host
+ * arrays: they touch no device and need no stream.
+ *
+ *   cp_rr_periodic_xi  expected pair counts of n uniformly random points in a
+ *       periodic cube of side boxsize (Section 1: the random-pair term is
+ *       analytic for a periodic cube), per bin [e_k, e_k+1):
+ *       n (n - 1) * (4 pi / 3) (e_k+1^3 - e_k^3) / L^3 ordered pairs, half of
+ *       that for CP_UNIQUE.  rr: nedges - 1 doubles.  The largest edge must
+ *       not exceed boxsize / 2 (minimum-image shells beyond are cut by the
+ *       cube): CP_ERR_INVALID_ARG.
+ *   cp_rr_periodic_wp  the same for the 2-D (r_p, pi) bins of countpairs_wp:
+ *       n (n - 1) * pi (e_k+1^2 - e_k^2) * 2 dpi / L^3 (both signs of the
+ *       line-of-sight separation), dpi = pimax / npibins, rr rp-major
+ *       (nedges - 1) * npibins doubles; needs pimax <= boxsize / 2 too.
+ *   cp_xi_natural  xi_k = (dd_k / dd_norm) / (rr_k / rr_norm) - 1 (Section 1,
+ *       eqn:xi), for nbins bins; with rr from cp_rr_periodic_* on the same
+ *       count convention both norms are 1; with pair-counted randoms they are
+ *       the pair totals, e.g. n_D (n_D - 1) and n_R (n_R - 1).  A bin with
+ *       rr_k = 0 gives NaN.
+ *   cp_wp_integrate  w_p(r_p,k) = 2 * sum_l xi(r_p,k, pi_l) * dpi, the
+ *       line-of-sight integral of Section 1 as a sum over the npibins bins of
+ *       width pimax / npibins; xi2d rp-major, wp nrpbins doubles.
+ *
+ * Errors: CP_ERR_INVALID_ARG (NULL arrays, bad edges, sizes, enums, norms).
+ */
+int cp_rr_periodic_xi(int64_t n, double boxsize, const double *edges, int nedges,
+                      int count_mode, double *rr);
+int cp_rr_periodic_wp(int64_t n, double boxsize, const double *rp_edges, int nedges,
+                      double pimax, int npibins, int count_mode, double *rr);
+int cp_xi_natural(const uint64_t *dd, double dd_norm, const double *rr, double rr_norm,
+                  int nbins, double *xi);
+int cp_wp_integrate(const double *xi2d, int nrpbins, int npibins, double pimax, double *wp);
+
 #ifdef __cplusplus
 }
 #endif

@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcountpairs.so")
-SOURCES = ["api.hip", "grid_kernels.hip", "pair_kernels.hip"]
+SOURCES = ["api.hip", "grid_kernels.hip", "pair_kernels.hip", "estimators.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -26,7 +26,7 @@ FLAGS = [
 
 def build(verbose: bool = False, jobs: int = 3) -> str:
     srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    objs = [os.path.join(CSRC, s.replace(".hip", ".o")) for s in SOURCES]
+    objs = [os.path.join(CSRC, os.path.splitext(s)[0] + ".o") for s in SOURCES]
     procs = []
     for src, obj in zip(srcs, objs):
         cmd = [HIPCC] + [f for f in FLAGS if f != "-shared"] + ["-c", src, "-o", obj]

@@ -52,6 +52,9 @@ static int fail(int code, const std::string &msg) {
   return code;
 }
 
+// error reporting for the host-only entry points in other files
+int report_error(int code, const char *msg) { return fail(code, msg); }
+
 #define HIPCHK(expr)                                                                   \
   do {                                                                                 \
     hipError_t e_ = (expr);                                                            \

@@ -24,6 +24,9 @@ constexpr int kQueues = 8;
 constexpr int kStatWords = 5 + kQueues;
 constexpr int kWStripe = 8;       // copies of each weight sum per wave (lane & 7)
 
+// Sets the calling thread's countpairs_last_error text and returns code.
+int report_error(int code, const char *msg);
+
 enum Mode { XI = 0, WP = 1 };
 enum Prec { F64 = 0, F32R = 1 };
 

@@ -29,7 +29,8 @@ EXPORTS = [
     "cp_default_options", "countpairs_xi", "countpairs_wp", "countpairs_cross",
     "countpairs_cross_wp", "countpairs_workspace_size", "countpairs_strerror",
     "countpairs_last_error", "countpairs_last_stats", "cp_plan_create", "cp_plan_execute",
-    "cp_plan_results", "cp_plan_stats", "cp_plan_destroy",
+    "cp_plan_results", "cp_plan_stats", "cp_plan_destroy", "cp_rr_periodic_xi",
+    "cp_rr_periodic_wp", "cp_xi_natural", "cp_wp_integrate",
 ]
 
 
@@ -109,6 +110,14 @@ def lib() -> ctypes.CDLL:
         L.cp_plan_stats.restype = ctypes.c_int
         L.cp_plan_destroy.argtypes = [ctypes.c_void_p]
         L.cp_plan_destroy.restype = ctypes.c_int
+        L.cp_rr_periodic_xi.argtypes = [ctypes.c_int64, ctypes.c_double, D, ctypes.c_int,
+                                        ctypes.c_int, D]
+        L.cp_rr_periodic_wp.argtypes = [ctypes.c_int64, ctypes.c_double, D, ctypes.c_int,
+                                        ctypes.c_double, ctypes.c_int, ctypes.c_int, D]
+        L.cp_xi_natural.argtypes = [U, ctypes.c_double, D, ctypes.c_double, ctypes.c_int, D]
+        L.cp_wp_integrate.argtypes = [D, ctypes.c_int, ctypes.c_int, ctypes.c_double, D]
+        for f in ("cp_rr_periodic_xi", "cp_rr_periodic_wp", "cp_xi_natural", "cp_wp_integrate"):
+            getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -396,3 +405,47 @@ def workspace_size(kind: str, n1: int, n2: int, edges, pimax: float = 0.0, npibi
     k = {"xi": 0, "wp": 1, "cross": 2, "cross_wp": 3}[kind]
     return int(lib().countpairs_workspace_size(k, int(n1), int(n2), _dp(e), e.size, float(pimax),
                                                 int(npibins), ctypes.byref(o)))
+
+
+# ------------------------------------------------------------- estimators
+# Host functions of the library (Section 1): analytic random pairs of a
+# periodic cube, the natural estimator and the w_p line-of-sight sum.
+
+def _mode(count_mode: str) -> int:
+    return {"ordered": CP_ORDERED, "unique": CP_UNIQUE}[count_mode]
+
+
+def cp_rr_periodic_xi(n: int, boxsize: float, edges, count_mode: str = "ordered") -> np.ndarray:
+    e = np.ascontiguousarray(edges, dtype=np.float64)
+    rr = np.zeros(max(1, e.size - 1), dtype=np.float64)
+    _check(lib().cp_rr_periodic_xi(int(n), float(boxsize), _dp(e), e.size, _mode(count_mode),
+                                   _dp(rr)))
+    return rr
+
+
+def cp_rr_periodic_wp(n: int, boxsize: float, rp_edges, pimax: float, npibins: int,
+                      count_mode: str = "ordered") -> np.ndarray:
+    e = np.ascontiguousarray(rp_edges, dtype=np.float64)
+    rr = np.zeros((max(1, e.size - 1), max(1, int(npibins))), dtype=np.float64)
+    _check(lib().cp_rr_periodic_wp(int(n), float(boxsize), _dp(e), e.size, float(pimax),
+                                   int(npibins), _mode(count_mode), _dp(rr)))
+    return rr
+
+
+def cp_xi_natural(dd, rr, dd_norm: float = 1.0, rr_norm: float = 1.0) -> np.ndarray:
+    d = np.ascontiguousarray(dd, dtype=np.uint64).ravel()
+    r = np.ascontiguousarray(rr, dtype=np.float64).ravel()
+    if d.size != r.size:
+        raise ValueError("dd and rr differ in size")
+    xi = np.zeros(d.size, dtype=np.float64)
+    _check(lib().cp_xi_natural(_up(d), float(dd_norm), _dp(r), float(rr_norm), d.size, _dp(xi)))
+    return xi.reshape(np.shape(dd))
+
+
+def cp_wp_integrate(xi2d, pimax: float) -> np.ndarray:
+    x = np.ascontiguousarray(xi2d, dtype=np.float64)
+    if x.ndim != 2:
+        raise ValueError("xi2d must be (rp bins, pi bins)")
+    wp = np.zeros(x.shape[0], dtype=np.float64)
+    _check(lib().cp_wp_integrate(_dp(x), x.shape[0], x.shape[1], float(pimax), _dp(wp)))
+    return wp

@@ -53,6 +53,35 @@ def test_headline_xi_weighted_full(native):
         _say(f"  {prec} ok, rechecks {g.stats['rechecks']}")
 
 
+def test_headline_estimators(native):
+    """xi(r) and w_p(r_p) of the 10^6-point Neyman-Scott catalogue from the GPU
+    counts and the library's estimators (natural estimator, analytic random
+    pairs of the periodic box, line-of-sight sum) against the generator's
+    closed-form correlation function."""
+    import math
+    from neyman_scott import ns_tolerance, ns_wp, ns_xi
+    c = synth.config2()
+    n, parents, sigma, box = c["cat"].n, 20_000, 1.5, 420.0
+    e = c["edges"]
+    d = native.to_device(c["cat"])
+    _say("headline estimators")
+    g = native.countpairs_xi(d, e, precision="fp32", periodic=True, boxsize=box)
+    rr = native.cp_rr_periodic_xi(n, box, e)
+    xi = native.cp_xi_natural(g.npairs, rr)
+    want = ns_xi(e, parents, sigma, box)
+    vol = 4.0 / 3.0 * math.pi * (e[1:] ** 3 - e[:-1] ** 3)
+    tol = ns_tolerance(want, rr, vol, parents, box)
+    assert np.all(np.abs(xi - want) < tol), (xi, want, tol)
+    pimax, npi = 40.0, 40
+    g = native.countpairs_wp(d, e, pimax, npi, precision="fp32", periodic=True, boxsize=box)
+    rr2 = native.cp_rr_periodic_wp(n, box, e, pimax, npi)
+    wp = native.cp_wp_integrate(native.cp_xi_natural(g.npairs.reshape(rr2.shape), rr2), pimax)
+    want = ns_wp(e, pimax, parents, sigma, box)
+    vol = math.pi * (e[1:] ** 2 - e[:-1] ** 2) * 2 * pimax
+    tol = 2 * pimax * ns_tolerance(want / (2 * pimax), rr2.sum(axis=1), vol, parents, box)
+    assert np.all(np.abs(wp - want) < tol), (wp, want, tol)
+
+
 def test_wp_full(native):
     c = synth.config3()
     _say("wp full: oracle")
