@@ -218,7 +218,9 @@ struct LanePt {
 // each group's loads issued one group ahead.  The main loop handles two
 // groups per trip so the two buffers alternate without copies; the stream
 // arrays are padded by 8 records, so the look-ahead never leaves the
-// allocation.  The body is called once per record with its values in SGPRs.
+// allocation.  The remainder goes one record at a time: one more copy of the
+// body instead of eight keeps the kernels small enough for the instruction
+// cache.  The body is called once per record with its values in SGPRs.
 
 #define CP_LOAD16(dst, src)                                                                    \
   _Pragma("unroll") for (int t_ = 0; t_ < 16; t_++) dst[t_] = (src)[t_];
@@ -229,26 +231,24 @@ template <typename F>
 __device__ inline void stream_f32(const float4 *base, int jb, int je, F &&body) {
   sfloat *p = (sfloat *)(base + jb);
   int j = jb;
-  float a[16];
-  CP_LOAD16(a, p);
-  while (j + 8 <= je) {
-    float b[16];
-    CP_LOAD16(b, p + 16);
-    CP_REC4(a, j, 0); CP_REC4(a, j, 1); CP_REC4(a, j, 2); CP_REC4(a, j, 3);
-    CP_LOAD16(a, p + 32);
-    CP_REC4(b, j + 4, 0); CP_REC4(b, j + 4, 1); CP_REC4(b, j + 4, 2); CP_REC4(b, j + 4, 3);
-    j += 8;
-    p += 32;
+  if (j + 8 <= je) {
+    float a[16];
+    CP_LOAD16(a, p);
+    do {
+      float b[16];
+      CP_LOAD16(b, p + 16);
+      CP_REC4(a, j, 0); CP_REC4(a, j, 1); CP_REC4(a, j, 2); CP_REC4(a, j, 3);
+      CP_LOAD16(a, p + 32);
+      CP_REC4(b, j + 4, 0); CP_REC4(b, j + 4, 1); CP_REC4(b, j + 4, 2); CP_REC4(b, j + 4, 3);
+      j += 8;
+      p += 32;
+    } while (j + 8 <= je);
   }
-  if (j < je) {
-    float b[16];
-    CP_LOAD16(b, p + 16);
-#pragma unroll
-    for (int u = 0; u < 4; u++)
-      if (j + u < je) CP_REC4(a, j, u);
-#pragma unroll
-    for (int u = 0; u < 4; u++)
-      if (j + 4 + u < je) CP_REC4(b, j + 4, u);
+  while (j < je) {
+    const float r0 = p[0], r1 = p[1], r2 = p[2], r3 = p[3];
+    body(j, r0, r1, r2, r3);
+    j++;
+    p += 4;
   }
 }
 
@@ -272,13 +272,11 @@ __device__ inline void stream_f64(const double4 *base, int jb, int je, F &&body)
     j += 4;
     p += 16;
   }
-  if (j < je) {
-    double b[8];
-    CP_LOAD8D(b, p + 8);
-    if (j < je) CP_REC2D(a, j, 0);
-    if (j + 1 < je) CP_REC2D(a, j, 1);
-    if (j + 2 < je) CP_REC2D(b, j + 2, 0);
-    if (j + 3 < je) CP_REC2D(b, j + 2, 1);
+  while (j < je) {
+    const double r0 = p[0], r1 = p[1], r2 = p[2], r3 = p[3];
+    body(j, r0, r1, r2, r3);
+    j++;
+    p += 4;
   }
 }
 
@@ -523,6 +521,26 @@ __device__ inline void loop_xi_f32(const PairParams &P, WaveArea A, const LanePt
 // wp, binary32 filter: the rp^2 estimate goes through the table, |dz| is
 // binned by multiplying with 1/dpi, and a pair whose fraction lies within
 // pi_delta of a pi edge, or whose |dz| is near pi_max, is uncertain.
+// Line-of-sight part of a binary32 wp decision: pi~ = |qz - rz| (cell-local
+// coordinates), its bin, whether it is surely below pi_max (inr: not surely
+// above), and whether binary32 cannot settle it (within the pi error bound
+// of a pi edge or of pi_max).
+struct WpPi {
+  bool inr, unc;
+  int l;
+};
+__device__ inline WpPi wp_pi(const PairParams &P, float rz, float qz) {
+  const float pz = fabsf(qz - rz);
+  const float f = pz * P.inv_dpi32;
+  const float fl = floorf(f);
+  const float fr = f - fl;
+  WpPi r;
+  r.l = min((int)fl, P.npi - 1);
+  r.inr = pz < P.pi_hi32;
+  r.unc = r.inr && ((fr < P.pi_delta) || (fr > 1.0f - P.pi_delta) || (pz >= P.pi_lo32));
+  return r;
+}
+
 struct WpHit {
   bool inr, unc;
   int slot, l;
@@ -534,17 +552,14 @@ __device__ inline WpHit wp_decide(const PairParams &P, const uint2 *tab32, const
   float v = __builtin_fmaf(rx, qx, ra);
   v = __builtin_fmaf(ry, qy, v);
   const float s = v + qw;
-  const float pz = fabsf(qz - rz);
+  const WpPi q = wp_pi(P, rz, qz);
   WpHit r;
-  r.inr = (s < P.AB32) && (pz < P.pi_hi32);
+  r.inr = (s < P.AB32) && q.inr;
   if (OWN) r.inr = r.inr && (j > L.iloc);
   const TabHit h = tab_lookup(tab32, P.tab32_lo, P.tab32_hi, P.tab_shift, s);
-  const float f = pz * P.inv_dpi32;
-  const float fl = floorf(f);
-  const float fr = f - fl;
-  r.l = min((int)fl, P.npi - 1);
+  r.l = q.l;
   r.slot = h.slot;
-  r.unc = r.inr && (h.unc || (fr < P.pi_delta) || (fr > 1.0f - P.pi_delta) || (pz >= P.pi_lo32));
+  r.unc = r.inr && (h.unc || q.unc);
   return r;
 }
 
@@ -683,6 +698,63 @@ __device__ inline void loop_xi_f64_two_w(const PairParams &P, WaveArea A, const 
   if (HIREAL) {
     atomicAdd(&A.hist[U.slot_hi * 64 + lane], nhi);
     add_w(A.hw + 2 * (U.slot_hi * kWStripe + (lane & (kWStripe - 1))), L.w * whi, L.w * rhi);
+  }
+}
+
+// xi, binary64, a unit whose pairs can only land in slot_lo .. slot_lo + 2:
+// two exact compares per pair against E_a = E[slot_lo], E_b = E[slot_lo + 1]
+// and register counts (and, weighted, register sums of w_j and w_j r per
+// slot, w_i applied once at the end), so the pairs need neither the decision
+// table nor LDS atomics.  A slot below E_0 is evaluated and then dropped;
+// HIREAL: the top slot is a bin, otherwise it lies beyond E_B and its pairs
+// skip the square root.  exec = valid lanes.
+template <bool SHIFT, int W, bool HIREAL>
+__device__ inline void loop_xi_f64_three(const PairParams &P, WaveArea A, const LanePt &L,
+                                         int lane, const Unit &U, const double *sE) {
+  const int s0 = U.slot_lo, nb = P.nb;
+  const double Ea = sE[s0], Eb = sE[s0 + 1];
+  const int wrapax[3] = {0, 0, 0};
+  uint32_t n0 = 0, n2 = 0;
+  double w0 = 0, w1 = 0, w2 = 0, r0 = 0, r1 = 0, r2 = 0;
+  stream_f64(U.pos, U.jb, U.je, [&](int, double ux, double uy, double uz, double uw) {
+    double dx, dy, dz;
+    ref_sep<SHIFT, false>(L.x, L.y, L.z, ux, uy, uz, U.S, wrapax, 0.0, 0.0, dx, dy, dz);
+    const double s64 = (dx * dx + dy * dy) + dz * dz;
+    const bool lo = s64 < Ea, hi = s64 >= Eb;
+    n0 += lo ? 1u : 0u;
+    n2 += hi ? 1u : 0u;
+    if (W && HIREAL) {
+      const double r = sep_sqrt(s64);
+      const double a = lo ? uw : 0.0;
+      const double c = hi ? uw : 0.0;
+      const double b = (uw - a) - c;   // exact: uw or 0
+      w0 += a;
+      r0 = __builtin_fma(a, r, r0);
+      w1 += b;
+      r1 = __builtin_fma(b, r, r1);
+      w2 += c;
+      r2 = __builtin_fma(c, r, r2);
+    } else if (W && !hi) {
+      const double r = sep_sqrt(s64);
+      const double a = lo ? uw : 0.0;
+      const double b = uw - a;         // exact: uw or 0
+      w0 += a;
+      r0 = __builtin_fma(a, r, r0);
+      w1 += b;
+      r1 = __builtin_fma(b, r, r1);
+    }
+  });
+  const uint32_t n1 = (uint32_t)(U.je - U.jb) - n0 - n2;
+  const int st = lane & (kWStripe - 1);
+  if (s0 >= 1) {
+    atomicAdd(&A.hist[s0 * 64 + lane], n0);
+    if (W) add_w(A.hw + 2 * (s0 * kWStripe + st), L.w * w0, L.w * r0);
+  }
+  atomicAdd(&A.hist[(s0 + 1) * 64 + lane], n1);
+  if (W) add_w(A.hw + 2 * ((s0 + 1) * kWStripe + st), L.w * w1, L.w * r1);
+  if (s0 + 2 <= nb) {
+    atomicAdd(&A.hist[(s0 + 2) * 64 + lane], n2);
+    if (W) add_w(A.hw + 2 * ((s0 + 2) * kWStripe + st), L.w * w2, L.w * r2);
   }
 }
 
@@ -986,36 +1058,45 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
           const float rxf = valid ? (float)(L.x - ox) : 1e18f;
           const float ryf = valid ? (float)(L.y - oy) : 1e18f;
           const float rzf = valid ? (float)(L.z - oz) : 1e18f;
+          // The binary32 loops take the shift as data: it only enters the
+          // rare binary64 re-evaluations, where adding a zero shift is exact,
+          // so one instance serves shifted and unshifted units (a smaller
+          // kernel, kinder to the instruction cache).
           if (MODE == XI) {
             const float ra = __builtin_fmaf(rzf, rzf, __builtin_fmaf(ryf, ryf, rxf * rxf));
             if (two) {
-              if (valid) {
-                if (shifted) loop_xi_f32_two<true>(P, A, L, lane, rxf, ryf, rzf, ra, U, sE, nrechk);
-                else loop_xi_f32_two<false>(P, A, L, lane, rxf, ryf, rzf, ra, U, sE, nrechk);
-              }
+              if (valid) loop_xi_f32_two<true>(P, A, L, lane, rxf, ryf, rzf, ra, U, sE, nrechk);
             } else if (!own && U.slot_hi == U.slot_lo + 2) {
-              if (valid) {
-                if (shifted) loop_xi_f32_three<true>(P, A, L, lane, rxf, ryf, rzf, ra, U, sE, nrechk);
-                else loop_xi_f32_three<false>(P, A, L, lane, rxf, ryf, rzf, ra, U, sE, nrechk);
-              }
+              if (valid) loop_xi_f32_three<true>(P, A, L, lane, rxf, ryf, rzf, ra, U, sE, nrechk);
             } else {
-#define CP_XI(O, SH) loop_xi_f32<O, SH>(P, A, L, lane, rxf, ryf, rzf, ra, U, tab32, sE, nrechk)
-              if (own) { if (shifted) CP_XI(true, true); else CP_XI(true, false); }
-              else { if (shifted) CP_XI(false, true); else CP_XI(false, false); }
-#undef CP_XI
+              if (own) loop_xi_f32<true, true>(P, A, L, lane, rxf, ryf, rzf, ra, U, tab32, sE, nrechk);
+              else loop_xi_f32<false, true>(P, A, L, lane, rxf, ryf, rzf, ra, U, tab32, sE, nrechk);
             }
-          } else {
+          } else if (!W) {
             const float ra = __builtin_fmaf(ryf, ryf, rxf * rxf);
-#define CP_WP(O, SH)                                                                       \
-  do {                                                                                     \
-    if (W) loop_wp_f32_w<O, SH>(P, A, L, lane, rxf, ryf, rzf, ra, U, tab32, sE, nrechk);   \
-    else loop_wp_f32<O, SH>(P, A, L, lane, rxf, ryf, rzf, ra, U, tab32, sE, nrechk);       \
-  } while (0)
+            if (own) loop_wp_f32<true, true>(P, A, L, lane, rxf, ryf, rzf, ra, U, tab32, sE, nrechk);
+            else loop_wp_f32<false, true>(P, A, L, lane, rxf, ryf, rzf, ra, U, tab32, sE, nrechk);
+          } else {
+            // weighted: every in-range pair takes the binary64 separation,
+            // where the shift costs an add per axis
+            const float ra = __builtin_fmaf(ryf, ryf, rxf * rxf);
+#define CP_WP(O, SH) loop_wp_f32_w<O, SH>(P, A, L, lane, rxf, ryf, rzf, ra, U, tab32, sE, nrechk)
             if (own) { if (shifted) CP_WP(true, true); else CP_WP(true, false); }
             else { if (shifted) CP_WP(false, true); else CP_WP(false, false); }
 #undef CP_WP
           }
-        } else if (two) {
+        } else if (PREC == F64 && MODE == XI && !own && !anywrap &&
+                   U.slot_hi == U.slot_lo + 2) {
+          if (valid) {
+            if (!W || U.slot_hi <= P.nb) {
+              if (shifted) loop_xi_f64_three<true, W, true>(P, A, L, lane, U, sE);
+              else loop_xi_f64_three<false, W, true>(P, A, L, lane, U, sE);
+            } else {
+              if (shifted) loop_xi_f64_three<true, W, false>(P, A, L, lane, U, sE);
+              else loop_xi_f64_three<false, W, false>(P, A, L, lane, U, sE);
+            }
+          }
+        } else if (PREC == F64 && two) {
           if (valid) {
             if (W) {
               if (U.slot_hi <= P.nb) {
