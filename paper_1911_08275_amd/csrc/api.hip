@@ -840,6 +840,7 @@ static int run(const Call &c, uint64_t *npairs, double *wsum, double *ravg) {
   P.EB = B.E[nb];
   P.pimax = c.pimax;
   P.dpi = B.dpi;
+  P.inv_dpi = 1.0 / B.dpi;
   P.npi = npi;
   P.inv_dpi32 = B.inv_dpi32;
   P.pi_delta = B.pi_delta;
@@ -1207,6 +1208,7 @@ static int batch_upload(cp_plan &pl, Batch &b) {
   P.EB = b.B.E[b.nb];
   P.pimax = b.pimax;
   P.dpi = b.B.dpi;
+  P.inv_dpi = 1.0 / b.B.dpi;
   P.npi = b.npi;
   P.inv_dpi32 = b.B.inv_dpi32;
   P.pi_delta = b.B.pi_delta;

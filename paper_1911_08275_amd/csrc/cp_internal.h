@@ -108,7 +108,7 @@ struct PairParams {
                              // difference is formed from the first (adds 2 u E_B)
   double EB;                 // E_B
   // wp
-  double pimax, dpi;
+  double pimax, dpi, inv_dpi;   // inv_dpi = fl(1 / dpi)
   int npi;
   float inv_dpi32, pi_delta, pi_lo32, pi_hi32;
   // flags

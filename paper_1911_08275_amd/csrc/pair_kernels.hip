@@ -71,13 +71,14 @@ __device__ inline int exact_slot(const double *E, int nb, double s) {
 }
 
 // Pi bin of a binary64 |dz| < pi_max: l with q_l <= pi < q_{l+1},
-// q_l = fl(l * dpi).
-__device__ inline int exact_pibin(double pz, double dpi, int npi) {
-  int l = (int)(pz / dpi);
-  if (l < 0) l = 0;
-  if (l > npi - 1) l = npi - 1;
-  while (l > 0 && pz < (double)l * dpi) l--;
-  while (l + 1 < npi && pz >= (double)(l + 1) * dpi) l++;
+// q_l = fl(l * dpi).  The product with fl(1 / dpi) lands within one of l
+// (|dz| / dpi < 257 and both roundings are relative), so one compare each
+// way against the exact q_l and q_{l+1} settles it without a division.
+__device__ inline int exact_pibin(double pz, double dpi, double inv_dpi, int npi) {
+  int l = (int)(pz * inv_dpi);
+  l = min(max(l, 0), npi - 1);
+  l -= (l > 0 && pz < (double)l * dpi) ? 1 : 0;
+  l += (l + 1 < npi && pz >= (double)(l + 1) * dpi) ? 1 : 0;
   return l;
 }
 
@@ -486,8 +487,10 @@ __device__ inline void loop_xi_f32_three(const PairParams &P, WaveArea A, const 
 }
 
 // xi, binary32, general unit: per-lane table lookup.  OWN: one of the tile's
-// own cells (auto-count), only j > i pairs.  Uncertain pairs are counted in
-// the first pass and re-evaluated in a second pass only when a lane has one.
+// own cells (auto-count), only j > i pairs.  An uncertain pair is
+// re-evaluated in binary64 on the spot: the branch is taken on the few
+// records where some lane has one, which costs less than streaming the unit
+// a second time (measured).
 template <bool OWN, bool SHIFT>
 __device__ inline void loop_xi_f32(const PairParams &P, WaveArea A, const LanePt &L, int lane,
                                    float rx, float ry, float rz, float ra, const Unit &U,
@@ -502,20 +505,14 @@ __device__ inline void loop_xi_f32(const PairParams &P, WaveArea A, const LanePt
     if (OWN) inr = inr && (j > L.iloc);
     if (inr) {
       const TabHit h = tab_lookup(tab32, lo, hi, sh, s);
-      // uncertain pairs add to the unused slot 0 here
-      atomicAdd(&A.hist[(h.unc ? 0 : h.slot) * 64 + lane], 1u);
-      nunc += h.unc ? 1u : 0u;
+      if (!h.unc) atomicAdd(&A.hist[h.slot * 64 + lane], 1u);
+      else {
+        recheck_xi<SHIFT>(A, L, lane, U, j, sE, nb);
+        nunc++;
+      }
     }
   });
-  if (nunc != 0u) {
-    stream_f32(U.strm, U.jb, U.je, [&](int j, float qx, float qy, float qz, float qw) {
-      const float s = gram3(rx, ry, rz, ra, qx, qy, qz, qw);
-      bool inr = s < AB;
-      if (OWN) inr = inr && (j > L.iloc);
-      if (inr && tab_lookup(tab32, lo, hi, sh, s).unc) recheck_xi<SHIFT>(A, L, lane, U, j, sE, nb);
-    });
-    nrechk += nunc;
-  }
+  nrechk += nunc;
 }
 
 // wp, binary32 filter: the rp^2 estimate goes through the table, |dz| is
@@ -575,11 +572,11 @@ __device__ inline void recheck_wp(const PairParams &P, WaveArea A, const LanePt 
   const double rp2 = dx * dx + dy * dy;
   const double pz64 = fabs(dz);
   if (pz64 < P.pimax && rp2 < P.EB)
-    atomicAdd(&A.hist[exact_slot(sE, P.nb, rp2) * P.npi + exact_pibin(pz64, P.dpi, P.npi)], 1u);
+    atomicAdd(&A.hist[exact_slot(sE, P.nb, rp2) * P.npi + exact_pibin(pz64, P.dpi, P.inv_dpi, P.npi)], 1u);
 }
 
-// wp, unweighted: certain pairs are counted in the first pass, uncertain
-// ones re-evaluated in a second pass only when a lane has one.
+// wp, unweighted: certain pairs are counted at once, uncertain ones
+// re-evaluated in binary64 on the spot (as in the general xi loop).
 template <bool OWN, bool SHIFT>
 __device__ inline void loop_wp_f32(const PairParams &P, WaveArea A, const LanePt &L, int lane,
                                    float rx, float ry, float rz, float ra, const Unit &U,
@@ -593,16 +590,13 @@ __device__ inline void loop_wp_f32(const PairParams &P, WaveArea A, const LanePt
     if (pre) {
       const WpHit h = wp_decide<OWN>(P, tab32, L, rx, ry, rz, ra, j, qx, qy, qz, qw);
       if (h.inr && !h.unc) atomicAdd(&A.hist[h.slot * npi + h.l], 1u);
-      nunc += h.unc ? 1u : 0u;
+      else if (h.unc) {
+        recheck_wp<SHIFT>(P, A, L, U, j, sE);
+        nunc++;
+      }
     }
   });
-  if (nunc != 0u) {
-    stream_f32(U.strm, U.jb, U.je, [&](int j, float qx, float qy, float qz, float qw) {
-      const WpHit h = wp_decide<OWN>(P, tab32, L, rx, ry, rz, ra, j, qx, qy, qz, qw);
-      if (h.unc) recheck_wp<SHIFT>(P, A, L, U, j, sE);
-    });
-    nrechk += nunc;
-  }
+  nrechk += nunc;
 }
 
 // wp, weighted: every in-range pair is evaluated in binary64 for its rp.
@@ -628,7 +622,7 @@ __device__ inline void loop_wp_f32_w(const PairParams &P, WaveArea A, const Lane
                  const double pz64 = fabs(dz);
                  keep = pz64 < P.pimax && rp2 < P.EB;
                  sl = exact_slot(sE, nb, rp2);
-                 ll = exact_pibin(pz64, P.dpi, npi);
+                 ll = exact_pibin(pz64, P.dpi, P.inv_dpi, npi);
                }
                if (keep) {
                  const double ww = L.w * uw;
@@ -787,7 +781,7 @@ __device__ inline void loop_f64(const PairParams &P, WaveArea A, const LanePt &L
       if (OWN) inr = inr && (j > L.iloc);
       if (inr) {
         const int slot = slot64(tab64, lo, hi, sh, sE, nb, rp2);
-        const int l = exact_pibin(pz64, P.dpi, npi);
+        const int l = exact_pibin(pz64, P.dpi, P.inv_dpi, npi);
         atomicAdd(&A.hist[slot * npi + l], 1u);
         if (W) {
           const double ww = L.w * uw;

@@ -167,3 +167,28 @@ def test_z_window_keeps_pairs_within_reach():
     hi = np.where(hi.astype(np.float64) < zh, np.nextafter(hi, np.float32(np.inf)), hi)
     assert np.all(xj[:, 2] >= lo.astype(np.float64))
     assert np.all(xj[:, 2] <= hi.astype(np.float64))
+
+
+def test_pi_bin_without_division():
+    """The binary64 pi bin of the kernels: l0 = trunc(pi * fl(1 / dpi)) clamped
+    to [0, npi), then one compare each way against q_l = fl(l dpi) and
+    q_{l+1}; against the definition q_l <= pi < q_{l+1} (q_0 = 0, top pi_max)
+    by search, on random and on edge-adjacent values of pi."""
+    rng = np.random.Generator(np.random.PCG64(31))
+    for _ in range(200):
+        pimax = float(rng.uniform(0.5, 300.0))
+        npi = int(rng.integers(1, 257))
+        dpi = pimax / npi
+        inv = 1.0 / dpi
+        q = np.array([0.0] + [l * dpi for l in range(1, npi)] + [pimax])
+        pz = list(rng.uniform(0.0, pimax, 200))
+        for l in range(1, npi):
+            for v in (q[l], np.nextafter(q[l], 0.0), np.nextafter(q[l], np.inf)):
+                pz.append(float(v))
+        pz = np.array([v for v in pz if 0.0 <= v < pimax])
+        l0 = np.clip((pz * inv).astype(np.int64), 0, npi - 1)
+        lq = np.array([l * dpi for l in range(npi + 1)])
+        l1 = l0 - ((l0 > 0) & (pz < lq[l0])).astype(np.int64)
+        l2 = l1 + ((l1 + 1 < npi) & (pz >= lq[np.minimum(l1 + 1, npi)])).astype(np.int64)
+        want = np.searchsorted(q[1:npi], pz, side="right")
+        assert np.array_equal(l2, want)
