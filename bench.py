@@ -453,7 +453,17 @@ def main():
             "sample": f"{len(idx)} random primaries (25%) of the headline catalogue against all "
                       f"1e6 points (cross count, weighted, periodic); {tcpu:.1f} s",
             "gpu_matches_oracle_on_sample": same, "wsum_max_rel_err": rel}
-        log(f"cpu oracle: {tcpu:.1f} s on {oracle.num_threads()} threads, match={same}")
+        # per-core rate: one thread on a 2 % sample
+        idx1 = np.sort(rng.choice(c2["cat"].n, c2["cat"].n // 50, replace=False))
+        sub1 = c2["cat"].subset(idx1)
+        t = time.perf_counter()
+        ref1 = oracle.xi(sub1, e2, periodic=True, box=420.0, other=c2["cat"], nthreads=1)
+        t1 = time.perf_counter() - t
+        out["cpu_baseline"]["one_thread"] = {
+            "value": float(ref1.npairs.sum()) / t1, "unit": "pairs/s",
+            "sample": f"{len(idx1)} random primaries (2%) against all 1e6 points; {t1:.1f} s"}
+        log(f"cpu oracle: {tcpu:.1f} s on {oracle.num_threads()} threads, match={same}; "
+            f"one thread {t1:.1f} s")
 
     print(json.dumps(out), flush=True)
 
