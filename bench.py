@@ -59,33 +59,38 @@ def time_steps(fn, steps, warmup):
     return dt, stats
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_pairs_xi_weighted_1e6_traffic.md")
+TRAFFIC_FILES = [os.path.join(ROOT, "profiles", f) for f in
+                 ("k_pairs_xi_weighted_1e6_traffic.md", "k_pairs_xi_weighted_1e6_traffic_r222.md")]
 KERNEL_SRC = os.path.join(ROOT, "paper_1911_08275_amd", "csrc", "pair_kernels.hip")
 
 
 def measured_traffic(refine):
-    """HBM bytes per launch of the headline pair kernel from the committed
-    FETCH_SIZE / WRITE_SIZE counter summary, or None when the kernel source
-    or the refine factors differ from those the counters were taken with."""
+    """HBM bytes per launch of the headline pair kernel from a committed
+    FETCH_SIZE / WRITE_SIZE counter summary taken at these refine factors, or
+    None when none matches the kernel source and the refine factors."""
     import hashlib
     try:
-        text = open(TRAFFIC_FILE).read()
+        src = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
     except OSError:
         return None
-    vals = {}
-    for line in text.splitlines():
-        if line.startswith("- ") and ":" in line:
-            k, v = line[2:].split(":", 1)
-            vals[k.strip()] = v.strip().strip("`")
-    try:
-        src = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
-        if vals.get("pair_kernels.hip sha256") != src:
-            return None
-        if vals.get("refine") != ",".join(str(r) for r in refine):
-            return None
-        return int(vals["fetch bytes per launch"]) + int(vals["write bytes per launch"])
-    except (KeyError, ValueError):
-        return None
+    want = ",".join(str(r) for r in refine)
+    for path in TRAFFIC_FILES:
+        try:
+            text = open(path).read()
+        except OSError:
+            continue
+        vals = {}
+        for line in text.splitlines():
+            if line.startswith("- ") and ":" in line:
+                k, v = line[2:].split(":", 1)
+                vals[k.strip()] = v.strip().strip("`")
+        if vals.get("pair_kernels.hip sha256") != src or vals.get("refine") != want:
+            continue
+        try:
+            return int(vals["fetch bytes per launch"]) + int(vals["write bytes per launch"])
+        except (KeyError, ValueError):
+            continue
+    return None
 
 
 def roofline(cand, inrange_unique, ms_pairs, weighted):
