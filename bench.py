@@ -112,7 +112,7 @@ def _median_call(fn, steps):
 
 def sweep_refine(native, steps):
     """Refine factors and bounding-box pruning on the headline catalogue
-    (the paper's refine-factor and pruning experiments of Section 3.1, on
+    (the paper's refine-factor and pruning experiments of Sections 3.1 and 3.2, on
     the MI355X): device time of one call per refine (r_x, r_y, r_z), pruning
     on and off, for weighted binary64 xi and unweighted binary32+recheck xi.
     Every configuration must give identical counts."""
@@ -158,7 +158,7 @@ def sweep_refine(native, steps):
 
 
 def sweep_rmax(native, steps):
-    """R_max scaling (the paper's Section 3.2 experiment, on the MI355X): xi
+    """R_max scaling (the paper's Section 3.3 experiment, on the MI355X): xi
     with 14 log bins over [0.1, R] and wp with pi_max = R, 1-wide pi bins, on
     the headline catalogue, binary64 and binary32+recheck, refine from the
     autotuner; the CPU oracle is timed on a random sample of primaries against

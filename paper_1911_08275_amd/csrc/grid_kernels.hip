@@ -181,7 +181,7 @@ __global__ __launch_bounds__(256) void k_assign(const PointsDev *pts, const Grid
 }
 
 // Cell order, z ascending inside each cell (Section 2.1 contiguous per-cell
-// storage; Section 2.2 z-sorted cells for late entry / early exit).  k_group
+// storage and z-sorted cells, used by the late entry / early exit of Section 2.2).  k_group
 // copies every point's (x, y, z, w) to its cell's range in the atomic order;
 // k_cellfin, one wave per cell, ranks the cell's points by z (ties by grouped
 // position, so the ranks form a permutation), writes them in that order
