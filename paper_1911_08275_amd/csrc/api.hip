@@ -889,7 +889,7 @@ static int run(const Call &c, uint64_t *npairs, double *wsum, double *ravg) {
     const int64_t nitems = (int64_t)ntiles * P.nsplit;
     for (int k = 0; k < kQueues; k++) {
       const int64_t len = nitems * (k + 1) / kQueues - nitems * k / kQueues;
-      if (hst[5 + k] < (unsigned long long)len)
+      if (hst[5 + k * kQStride] < (unsigned long long)len)
         return fail(CP_ERR_INTERNAL, "work queue not drained");
     }
   }

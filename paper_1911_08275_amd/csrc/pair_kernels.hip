@@ -845,7 +845,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
       while (victim < kQueues) {
         const int k = (home + victim) % kQueues;
         const int64_t qb = nitems * k / kQueues, qe = nitems * (k + 1) / kQueues;
-        const int64_t i = (int64_t)atomicAdd(&heads[k], 1ull);
+        const int64_t i = (int64_t)atomicAdd(&heads[k * kQStride], 1ull);
         if (qb + i < qe) {
           tix = qb + i;
           break;
