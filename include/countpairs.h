@@ -120,7 +120,8 @@ void cp_default_options(cp_options *o);
 
 /*
  * xi(r) auto-count of d (Section 1.1 eqn:separations, first case).
- *   edges   nedges >= 2 host doubles, finite, strictly increasing, edges[0] >= 0
+ *   edges   2 <= nedges <= 61 host doubles (at most 60 bins), finite, strictly
+ *           increasing, edges[0] >= 0
  *   npairs  nedges-1 host uint64 counts (required)
  *   wsum, ravg  nedges-1 host doubles each, written when need_ravg (then required)
  * Fewer than two points give zero counts and CP_OK.
@@ -133,9 +134,13 @@ int countpairs_xi(const cp_points *d, const double *edges, int nedges,
  * wp auto-count: 2-D histogram xi(rp, pi) (Section 1.1 eqn:separations,
  * second case; pi_max filter), line of sight z.
  *   rp_edges  as edges above, bins in rp
- *   pimax     > 0; npibins >= 1 equal pi bins in [0, pimax)
+ *   pimax     > 0; 1 <= npibins <= 256 equal pi bins in [0, pimax)
  *   npairs    (nedges-1) * npibins host uint64, rp-major
  *   wsum, rpavg  same shape, when need_ravg
+ * Each wave of the pair kernel keeps the whole 2-D histogram in LDS:
+ * (nedges + 1) * npibins * 4 bytes, plus 16 bytes per entry when need_ravg,
+ * must stay under ~159 KB (fewer waves per workgroup are used as it grows);
+ * beyond that the call fails with CP_ERR_INVALID_ARG.
  */
 int countpairs_wp(const cp_points *d, const double *rp_edges, int nedges,
                   double pimax, int npibins, const cp_options *o,

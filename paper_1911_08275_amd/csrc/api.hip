@@ -471,6 +471,20 @@ static int num_cus() {
   return g_num_cus;
 }
 
+// Waves per pair-kernel workgroup: four, or fewer when the per-wave
+// histograms (w_p with many bins, weighted) would not fit the 160 KB of LDS;
+// 0 when not even one wave's fits.
+static int pick_waves(const LdsLayout &LY, size_t *lds) {
+  for (int nw = 4; nw >= 1; nw--) {
+    const size_t l = LY.common + (size_t)nw * LY.wave_bytes;
+    if (l <= 160 * 1024) {
+      *lds = l;
+      return nw;
+    }
+  }
+  return 0;
+}
+
 template <int MODE, int PREC, int W>
 static int launch_pairs_t(hipStream_t st, const PairParams &P, size_t lds, int nwaves) {
   auto kern = k_pairs<MODE, PREC, W>;
@@ -854,10 +868,10 @@ static int run(const Call &c, uint64_t *npairs, double *wsum, double *ravg) {
   P.hwr = d_hwr;
   P.stats = d_stats;
   P.hist_stride = nout;
-  const int nwaves = 4;
   const LdsLayout LY = lds_layout(c.mode, prec, weighted, n32, n64, nb, npi);
-  const size_t lds = LY.common + nwaves * LY.wave_bytes;
-  if (lds > 160 * 1024) return fail(CP_ERR_INVALID_ARG, "too many bins for the LDS budget");
+  size_t lds = 0;
+  const int nwaves = pick_waves(LY, &lds);
+  if (!nwaves) return fail(CP_ERR_INVALID_ARG, "too many bins for the LDS budget");
   if ((rc = launch_pairs(st, c.mode, prec, weighted, P, lds, nwaves))) return rc;
   HIPCHK(hipEventRecord(ev[2], st));
 
@@ -1122,11 +1136,10 @@ static int batch_prepare(cp_plan &pl, Batch &b, int mode, int prec, const double
   b.ncol_tot = b.ncol * pl.nmock;
   b.segs.push_back({0, 0, b.ncol_tot});
   b.maxtiles = max_tiles_bound(b.npts_tot, b.ncell_tot, b.ncol_tot);
-  b.nwaves = 4;
   const LdsLayout LY = lds_layout(mode, b.prec, 0, (int)b.B.t32.e.size(),
                                        (int)b.B.t64.e.size(), b.nb, b.npi);
-  b.lds = LY.common + b.nwaves * LY.wave_bytes;
-  if (b.lds > 160 * 1024) return fail(CP_ERR_INVALID_ARG, "too many bins for the LDS budget");
+  b.nwaves = pick_waves(LY, &b.lds);
+  if (!b.nwaves) return fail(CP_ERR_INVALID_ARG, "too many bins for the LDS budget");
   return CP_OK;
 }
 

@@ -278,6 +278,36 @@ def test_pruning_off_equals_on(native, prec):
         _check(g, refc)
 
 
+def test_maximum_bins(native):
+    """The largest histograms: 60 xi bins (weighted), a 60 x 256 w_p histogram
+    (64 KB per wave, so the kernel runs fewer waves per workgroup), a weighted
+    w_p of 20 x 100 bins (three waves per workgroup), and a weighted 60 x 256
+    w_p, whose per-wave histograms cannot fit the LDS: a clean error."""
+    cat = synth.clustered(30_000, 600, 1.5, 420.0, seed=44, weights=True)
+    d = native.to_device(cat)
+    e60 = synth.log_edges(0.1, 25.0, 60)
+    ref = oracle.xi(cat, e60, periodic=True, box=420.0)
+    for prec in ("fp64", "fp32"):
+        _say("max bins xi", prec)
+        g = native.countpairs_xi(d, e60, precision=prec, periodic=True, boxsize=420.0,
+                                 need_ravg=True)
+        _check(g, ref, weighted=True)
+    refw = oracle.wp(cat, e60, 40.0, 256, periodic=True, box=420.0)
+    for prec in ("fp64", "fp32"):
+        _say("max bins wp", prec)
+        g = native.countpairs_wp(d, e60, 40.0, 256, precision=prec, periodic=True, boxsize=420.0)
+        _check(g, refw)
+    e20 = synth.log_edges(0.1, 25.0, 20)
+    refw = oracle.wp(cat, e20, 40.0, 100, periodic=True, box=420.0)
+    for prec in ("fp64", "fp32"):
+        _say("weighted wp 20 x 100", prec)
+        g = native.countpairs_wp(d, e20, 40.0, 100, precision=prec, periodic=True,
+                                 boxsize=420.0, need_ravg=True)
+        _check(g, refw, weighted=True)
+    with pytest.raises(native.CountpairsError, match="LDS"):
+        native.countpairs_wp(d, e60, 40.0, 256, periodic=True, boxsize=420.0, need_ravg=True)
+
+
 def test_tiny_inputs(native):
     import torch
     edges = [0.0, 1.0, 2.0]
