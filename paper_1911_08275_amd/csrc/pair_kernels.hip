@@ -1,29 +1,37 @@
-// Pair kernels: one persistent launch drains a queue of primary tiles.
+// Pair kernels: one persistent launch drains work queues of items.
 //
 // Work decomposition (MI355X, wave64).  A tile is <= 64 points of one cell
-// column; lane l of a wave holds tile point l for the whole tile.  The wave
-// walks the neighbouring cells of the tile (Section 1.2: all pairs within
-// R_max lie in the neighbouring cells; Section 2.1: for an auto-count only
-// unique pairs of cells, here unique pairs of points by sorted index), skips
-// cells whose bounding box is too far from the tile's (Section 2.2, minimum
-// possible separation), and streams each remaining cell's points through
-// the scalar cache so every VALU instruction of the inner loop takes one
-// wave-uniform operand from SGPRs and one per-lane operand from VGPRs.
+// column; lane l of a wave holds tile point l.  An item is one tile and one
+// x offset of its neighbour search; items sit in 8 queues, one per XCD, each
+// a contiguous share of the box, drained by that XCD's waves first.  For an
+// item the wave tests the neighbouring cells 64 at a time (Section 1.2: all
+// pairs within R_max lie in the neighbouring cells; Section 2.1: for an
+// auto-count only unique pairs of cells, here unique pairs of points by
+// sorted index), skips cells whose bounding box is too far from the tile's
+// (Section 2.2, minimum possible separation), cuts each remaining (tile,
+// cell) unit to a z-window on the z-sorted cell (Section 2.2, late entry and
+// early exit), and streams the unit's points through the scalar cache, so
+// every VALU instruction of the inner loop takes one wave-uniform operand
+// from SGPRs and one per-lane operand from VGPRs.
 //
 // Inner loop, binary32 mode.  Coordinates are held relative to the streamed
 // cell's centre, so the squared separation is evaluated as
 //   s~ = |r|^2 + |p|^2 - 2 r.p     (r: tile point, p: streamed point)
 // in three FMAs and one add; the stream record carries (-2p, |p|^2).  An
 // error bound eps on |s~ - s| (s the binary64 value of the reference formula)
-// turns each edge E_k into an uncertain band [E_k - eps, E_k + eps); a
-// 2-word LDS lookup indexed by the exponent and top mantissa bits of s~ gives
-// the bin, or flags the pair for re-evaluation in binary64 with the reference
-// formula.  Counts therefore equal the binary64 counts exactly.
+// turns each edge E_k into an uncertain band; pairs inside a band are
+// re-evaluated in binary64 with the reference formula, so counts equal the
+// binary64 counts exactly.
 //
-// Binning (Section 2.2 "Updating the histogram"): the paper scans bins from
+// Binning (Section 2.2 "Updating the histogram").  The paper scans bins from
 // the outermost down with vector masks and popcounts; on a 64-wide wave that
-// scan runs about as deep as the innermost bin any lane needs, so here each
-// lane instead owns a private row of LDS counters indexed by its bin.
+// scan runs about as deep as the innermost bin any lane needs.  Here the
+// unit's separation bounds pick the loop: a unit inside one bin is counted
+// without separations, units spanning two or three slots decide each pair
+// with one or two compares into register counters (and register weight
+// sums), and other units look the bin up in a 2-word LDS table indexed by
+// the exponent and top mantissa bits of the separation, counting into a
+// private row of LDS counters per lane.
 #include "cp_internal.h"
 
 #include <float.h>
