@@ -388,6 +388,23 @@ def test_plan_matches_oracle(native):
         plan.close()
 
 
+def test_plan_pruning_off_equals_on(native):
+    """The plan path with the bounding-box tests switched off gives the same
+    counts for every catalogue and statistic."""
+    cats = _mock_set()
+    xe = synth.log_edges(0.1, 25.0, 14)
+    devs = [native.to_device(c) for c in cats]
+    _say("plan prune on/off")
+    res = []
+    for flag in (False, True):
+        plan = native.Plan(devs, xi_edges=xe, wp_edges=xe, pimax=40.0, npibins=40,
+                           precision="fp32", periodic=True, boxsize=420.0, no_prune=flag)
+        plan.execute()
+        res.append(plan.results())
+        plan.close()
+    assert (res[0][0] == res[1][0]).all() and (res[0][1] == res[1][1]).all()
+
+
 def test_plan_graph_replays(native):
     """Replays of the captured graph, with eager work in between, all equal
     the eager result."""
