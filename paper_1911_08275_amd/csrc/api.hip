@@ -251,6 +251,62 @@ static Geometry choose_geometry(int mode, bool periodic, double box, const doubl
   return g;
 }
 
+// Queue items of a tile.  The tile's neighbour columns are listed in a fixed
+// order (the kernel decodes the same order): for an auto-count the half-shell
+// of Section 2.1 taken geometrically -- the tile's own column first (searched
+// forward in z only), then the columns at x offset 0 and y offset 1..r_y, then
+// x offsets 1..r_x with every y offset; for a cross-count the whole
+// (2 r_x + 1) x (2 r_y + 1) block.  Each cell pair of the box is met once
+// because every periodic axis has at least 2 r + 1 cells or is a single
+// wrapped cell.  The list is cut into consecutive chunks of about equal
+// estimated cost, one queue item each, so that no item is much heavier than
+// the rest: a column whose x-y gap to the tile's column is g costs about
+// (1 - g^2 / R^2)^2 of an adjacent one (fitted to measured per-column times),
+// the own column 0.9, and a chunk aims at 2.2 adjacent columns.
+static void split_columns(const Geometry &g, bool autoc, double reach, PairParams &P) {
+  const int rx = g.r[0], ry = g.r[1], ncy = 2 * ry + 1;
+  const int ncols = autoc ? 1 + ry + rx * ncy : (2 * rx + 1) * ncy;
+  std::vector<double> cum(ncols + 1, 0.0);
+  for (int c = 0; c < ncols; c++) {
+    int ox, oy;
+    if (autoc) {
+      if (c <= ry) {
+        ox = 0;
+        oy = c;
+      } else {
+        ox = 1 + (c - 1 - ry) / ncy;
+        oy = (c - 1 - ry) % ncy - ry;
+      }
+    } else {
+      ox = c / ncy - rx;
+      oy = c % ncy - ry;
+    }
+    double w;
+    if (autoc && c == 0) {
+      w = 0.9;
+    } else {
+      const double gx = std::max(std::abs(ox) - 1, 0) * g.cs[0];
+      const double gy = std::max(std::abs(oy) - 1, 0) * g.cs[1];
+      const double t = reach > 0 ? 1.0 - (gx * gx + gy * gy) / (reach * reach) : 1.0;
+      w = std::max(t > 0 ? t * t : 0.0, 0.02);
+    }
+    cum[c + 1] = cum[c] + w;
+  }
+  const double tot = cum[ncols];
+  int m = (int)std::lround(tot / 2.2);
+  m = std::max(1, std::min(m, std::min(kMaxChunks, ncols)));
+  P.nsplit = m;
+  P.chunk[0] = 0;
+  for (int k = 1; k < m; k++) {
+    const double target = tot * k / m;
+    int best = P.chunk[k - 1] + 1;
+    for (int b = best; b <= ncols - (m - k); b++)
+      if (std::fabs(cum[b] - target) < std::fabs(cum[best] - target)) best = b;
+    P.chunk[k] = best;
+  }
+  P.chunk[m] = ncols;
+}
+
 static GridGeom to_dev_geom(const Geometry &g, bool periodic, double box, int64_t pbase,
                             int64_t cbase, int64_t sbase, int64_t npts, int64_t colbase) {
   GridGeom G;
@@ -477,7 +533,7 @@ static int num_cus() {
 static int pick_waves(const LdsLayout &LY, size_t *lds) {
   for (int nw = 4; nw >= 1; nw--) {
     const size_t l = LY.common + (size_t)nw * LY.wave_bytes;
-    if (l <= 160 * 1024) {
+    if (l + kStaticLds <= 160 * 1024) {
       *lds = l;
       return nw;
     }
@@ -828,7 +884,7 @@ static int run(const Call &c, uint64_t *npairs, double *wsum, double *ravg) {
   memset(&P, 0, sizeof(P));
   P.tiles = S1.tiles;
   P.ntiles = S1.coloff + ncol;
-  P.nsplit = 2 * g.r[0] + 1;
+  split_columns(g, autoc, rmax, P);
   P.geom1 = &d_sm->geom[0];
   P.geom2 = &d_sm->geom[1];
   P.pos1 = S1.pos;
@@ -1195,7 +1251,7 @@ static int batch_upload(cp_plan &pl, Batch &b) {
   memset(&P, 0, sizeof(P));
   P.tiles = b.S.tiles;
   P.ntiles = b.S.coloff + b.ncol_tot;
-  P.nsplit = 2 * b.g.r[0] + 1;
+  split_columns(b.g, true, std::sqrt(b.B.E[b.nb]), P);
   P.geom1 = b.d_geom;
   P.geom2 = b.d_geom;
   P.pos1 = b.S.pos;

@@ -27,6 +27,9 @@ constexpr int kQueues = 8;
 // 1.25 ms with packed heads, 0.71 ms with spread ones).
 constexpr int kQStride = 512;
 constexpr int kStatWords = 5 + kQueues * kQStride;
+// Most queue items per tile (chunks of the tile's neighbour-column list).
+constexpr int kMaxChunks = 32;
+constexpr int kStaticLds = 256;  // LDS the pair kernel declares statically (queue mask)
 constexpr int kWStripe = 8;       // copies of each weight sum per wave (lane & 7)
 
 // Sets the calling thread's countpairs_last_error text and returns code.
@@ -86,8 +89,8 @@ struct PairParams {
   // work queue
   const Tile *tiles;
   const int *ntiles;         // device: number of tiles in the queue
-  int nsplit;                // queue items per tile: one per x offset of the
-                             // neighbour search (2 r_x + 1 slabs)
+  int nsplit;                // queue items per tile: chunks of its neighbour-column list
+  int chunk[kMaxChunks + 1]; // chunk k covers list columns [chunk[k], chunk[k + 1])
   // geometry (indexed by tile.mock); set 2 is the searched (streamed) set
   const GridGeom *geom1;
   const GridGeom *geom2;

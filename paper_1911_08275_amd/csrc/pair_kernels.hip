@@ -2,17 +2,18 @@
 //
 // Work decomposition (MI355X, wave64).  A tile is <= 64 points of one cell
 // column; lane l of a wave holds tile point l.  An item is one tile and one
-// x offset of its neighbour search; items sit in 8 queues, one per XCD, each
-// a contiguous share of the box, drained by that XCD's waves first.  For an
-// item the wave tests the neighbouring cells 64 at a time (Section 1.2: all
-// pairs within R_max lie in the neighbouring cells; Section 2.1: for an
-// auto-count only unique pairs of cells, here unique pairs of points by
-// sorted index), skips cells whose bounding box is too far from the tile's
-// (Section 2.2, minimum possible separation), cuts each remaining (tile,
-// cell) unit to a z-window on the z-sorted cell (Section 2.2, late entry and
-// early exit), and streams the unit's points through the scalar cache, so
-// every VALU instruction of the inner loop takes one wave-uniform operand
-// from SGPRs and one per-lane operand from VGPRs.
+// chunk of its list of neighbour columns (chunks of about equal cost); items
+// sit in 8 queues, one per XCD, each a contiguous share of the box, drained
+// by that XCD's waves first.  For an item the wave tests the neighbouring
+// cells 64 at a time (Section 1.2: all pairs within R_max lie in the
+// neighbouring cells; Section 2.1: for an auto-count only unique pairs of
+// cells -- a geometric half-shell -- and within the tile's own cells unique
+// pairs of points by sorted index), skips cells whose bounding box is too
+// far from the tile's (Section 2.2, minimum possible separation), cuts each
+// remaining (tile, cell) unit to a z-window on the z-sorted cell (Section
+// 2.2, late entry and early exit), and streams the unit's points through the
+// scalar cache, so every VALU instruction of the inner loop takes one
+// wave-uniform operand from SGPRs and one per-lane operand from VGPRs.
 //
 // Inner loop, binary32 mode.  Coordinates are held relative to the streamed
 // cell's centre, so the squared separation is evaluated as
@@ -171,10 +172,16 @@ __device__ inline void flush_hist(const PairParams &P, WaveArea A, int mock, int
   const int nb = P.nb, NS = P.nslots;
   unsigned long long *gh = P.hist + (int64_t)mock * P.hist_stride;
   if (MODE == XI) {
+    // lane s - 1 takes slot s's wave total, and one atomic instruction adds
+    // them all: every wave's totals land in the same few lines of the output,
+    // and per-slot atomics from one lane (one memory request each) queued
+    // there for tens of microseconds at the end of a launch
+    unsigned long long mine = 0;
     for (int s = 1; s <= nb; s++) {
-      unsigned long long v = wave_sum_u64((unsigned long long)A.hist[s * 64 + lane]);
-      if (lane == 0 && v) atomicAdd(gh + (s - 1), v);
+      const unsigned long long v = wave_sum_u64((unsigned long long)A.hist[s * 64 + lane]);
+      if (lane == s - 1) mine = v;
     }
+    if (lane < nb && mine) atomicAdd(gh + lane, mine);
     if (W && lane >= 1 && lane <= nb) {
       double a = 0.0, b = 0.0;
       for (int c = 0; c < kWStripe; c++) {
@@ -807,6 +814,13 @@ __device__ inline void loop_f64(const PairParams &P, WaveArea A, const LanePt &L
 template <int MODE, int PREC, int W>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_pairs(PairParams P) {
   extern __shared__ __align__(16) unsigned char smem[];
+  // bit k: a wave of this workgroup found queue k drained.  Queues only
+  // drain, so the other waves skip it without another device-scope atomic:
+  // at the end of a launch every wave otherwise tried all eight heads, and
+  // those atomics queued at the memory side with other waves' misses behind
+  // them.
+  __shared__ uint32_t qdrained;
+  if (threadIdx.x == 0) qdrained = 0u;
   const int lane = threadIdx.x & 63;
   const int wid = threadIdx.x >> 6;
   const int n32 = PREC == F32R ? P.tab32_hi - P.tab32_lo + 1 : 0;
@@ -853,18 +867,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
       while (victim < kQueues) {
         const int k = (home + victim) % kQueues;
         const int64_t qb = nitems * k / kQueues, qe = nitems * (k + 1) / kQueues;
+        if ((*(volatile uint32_t *)&qdrained >> k) & 1u) {
+          victim++;
+          continue;
+        }
         const int64_t i = (int64_t)atomicAdd(&heads[k * kQStride], 1ull);
         if (qb + i < qe) {
           tix = qb + i;
           break;
         }
+        atomicOr(&qdrained, 1u << k);
         victim++;
       }
     }
     tix = uni64(__shfl(tix, 0));
     if (tix < 0) break;
-    // item = (tile, x offset of the neighbour search): consecutive items
-    // share a tile, so its slabs run on different waves at the same time
+    // item = (tile, chunk of its neighbour columns): consecutive items share
+    // a tile, so its chunks run on different waves at the same time
     const int64_t tile_ix = tix / nsplit;
     const int part = (int)(tix - tile_ix * nsplit);
     const Tile T = P.tiles[tile_ix];
@@ -901,7 +920,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
     const int rx = G2.r[0], ry = G2.r[1], rz = G2.r[2];
     const int nzr = (tz1 - tz0) + 2 * rz + 1;
     const int ncy = 2 * ry + 1;
-    const int total = part <= 2 * rx ? ncy * nzr : 0;
+    const int col0 = P.chunk[part];
+    const int total = (P.chunk[part + 1] - col0) * nzr;
     const double box = G2.box, half = G2.halfbox;
     const int wrapax[3] = {G2.wrap[0], G2.wrap[1], G2.wrap[2]};
     const bool anywrap = wrapax[0] | wrapax[1] | wrapax[2];
@@ -911,30 +931,39 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
       const int t = base + lane;
       int keep = 0, pruned = 0, cell = 0, packed = 0, slots = 0, win = 0, wzlo = 0, wzhi = 0;
       if (t < total) {
+        // column of the tile's list (order fixed by the host's split) and
+        // z offset; an auto-count searches its own column forward in z only,
+        // cells inside the tile's own z range with a per-pair j > i test
         const int oz = t % nzr;
-        const int oy = t / nzr;
-        const int ox = part;
-        int X = cx + ox - rx, Y = cy + oy - ry, Z = tz0 - rz + oz;
+        const int col = col0 + t / nzr;
+        int ox, oy;
+        if (P.autocorr) {
+          if (col <= ry) {
+            ox = 0;
+            oy = col;
+          } else {
+            ox = 1 + (col - 1 - ry) / ncy;
+            oy = (col - 1 - ry) % ncy - ry;
+          }
+        } else {
+          ox = col / ncy - rx;
+          oy = col % ncy - ry;
+        }
+        int X = cx + ox, Y = cy + oy, Z = tz0 - rz + oz;
         int sx = 0, sy = 0, sz = 0;
         bool ok = true;
+        int own = 0;
+        if (P.autocorr && col == 0) {
+          if (oz < rz) ok = false;
+          else if (oz - rz <= tz1 - tz0) own = 1;
+        }
         if (X < 0) { if (G2.periodic) { X += G2.n[0]; sx = -1; } else ok = false; }
         else if (X >= G2.n[0]) { if (G2.periodic) { X -= G2.n[0]; sx = 1; } else ok = false; }
         if (Y < 0) { if (G2.periodic) { Y += ny; sy = -1; } else ok = false; }
         else if (Y >= ny) { if (G2.periodic) { Y -= ny; sy = 1; } else ok = false; }
         if (Z < 0) { if (G2.periodic) { Z += nz; sz = -1; } else ok = false; }
         else if (Z >= nz) { if (G2.periodic) { Z -= nz; sz = 1; } else ok = false; }
-        int own = 0;
-        if (ok) {
-          cell = (X * ny + Y) * nz + Z;
-          const int colp = X * ny + Y;
-          if (P.autocorr) {
-            if (colp < tcol) ok = false;
-            else if (colp == tcol) {
-              if (Z < tz0) ok = false;
-              else if (Z <= tz1) own = 1;
-            }
-          }
-        }
+        if (ok) cell = (X * ny + Y) * nz + Z;
         if (ok) {
           const int b = P.cstart2[G2.sbase + cell], e = P.cstart2[G2.sbase + cell + 1];
           if (e == b) {
@@ -1129,12 +1158,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
   }
   if (cur_mock >= 0) flush_hist<MODE, W>(P, A, cur_mock, lane);
   const unsigned long long rc = wave_sum_u64((unsigned long long)nrechk);
-  if (lane == 0) {
-    if (st_cand) atomicAdd(P.stats + 0, st_cand);
-    if (rc) atomicAdd(P.stats + 1, rc);
-    if (st_cells) atomicAdd(P.stats + 2, st_cells);
-    if (st_pruned) atomicAdd(P.stats + 3, st_pruned);
-  }
+  // one atomic instruction for the four statistics (lane k adds word k)
+  const unsigned long long sv = lane == 0 ? st_cand : lane == 1 ? rc : lane == 2 ? st_cells : st_pruned;
+  if (lane < 4 && sv) atomicAdd(P.stats + lane, sv);
 }
 
 template __global__ void k_pairs<XI, F32R, 0>(PairParams);
