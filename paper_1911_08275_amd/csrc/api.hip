@@ -261,9 +261,16 @@ static Geometry choose_geometry(int mode, bool periodic, double box, const doubl
 // wrapped cell.  The list is cut into consecutive chunks of about equal
 // estimated cost, one queue item each, so that no item is much heavier than
 // the rest: a column whose x-y gap to the tile's column is g costs about
-// (1 - g^2 / R^2)^2 of an adjacent one (fitted to measured per-column times),
-// the own column 0.9, and a chunk aims at 2.2 adjacent columns.
-static void split_columns(const Geometry &g, bool autoc, double reach, PairParams &P) {
+// (1 - g^2 / R^2)^2 of an adjacent one (fitted to measured per-column times)
+// and the own column 0.9.  A chunk aims at 4.5 sqrt(137 / c) adjacent columns,
+// kept within [2.2, 12], where c is the expected number of searched points in
+// one adjacent column's reach (density npts2 / box volume) times the cost
+// factor (2 for binary64, 2 for weights, 2.5 for w_p): light items are
+// dominated by the per-item set-up and want more columns, heavy ones want the
+// finer split for the end of the queue (fitted to timings from R_max = 5 to
+// 100).
+static void split_columns(const Geometry &g, bool autoc, double reach, double reach_z,
+                          double npts2, double cost, PairParams &P) {
   const int rx = g.r[0], ry = g.r[1], ncy = 2 * ry + 1;
   const int ncols = autoc ? 1 + ry + rx * ncy : (2 * rx + 1) * ncy;
   std::vector<double> cum(ncols + 1, 0.0);
@@ -293,7 +300,13 @@ static void split_columns(const Geometry &g, bool autoc, double reach, PairParam
     cum[c + 1] = cum[c] + w;
   }
   const double tot = cum[ncols];
-  int m = (int)std::lround(tot / 2.2);
+  const double vol = g.ext[0] * g.ext[1] * g.ext[2];
+  double per = 2.2;
+  if (vol > 0 && npts2 > 0) {
+    const double c = npts2 / vol * g.cs[0] * g.cs[1] * (2.0 * reach_z + g.cs[2]) * cost;
+    per = std::min(12.0, std::max(2.2, 4.5 * std::sqrt(137.0 / std::max(c, 1e-9))));
+  }
+  int m = (int)std::lround(tot / per);
   m = std::max(1, std::min(m, std::min(kMaxChunks, ncols)));
   P.nsplit = m;
   P.chunk[0] = 0;
@@ -884,7 +897,8 @@ static int run(const Call &c, uint64_t *npairs, double *wsum, double *ravg) {
   memset(&P, 0, sizeof(P));
   P.tiles = S1.tiles;
   P.ntiles = S1.coloff + ncol;
-  split_columns(g, autoc, rmax, P);
+  split_columns(g, autoc, rmax, c.mode == XI ? rmax : c.pimax, (double)p2.n,
+                (prec == F64 ? 2.0 : 1.0) * (weighted ? 2.0 : 1.0) * (c.mode == WP ? 2.5 : 1.0), P);
   P.geom1 = &d_sm->geom[0];
   P.geom2 = &d_sm->geom[1];
   P.pos1 = S1.pos;
@@ -1251,7 +1265,9 @@ static int batch_upload(cp_plan &pl, Batch &b) {
   memset(&P, 0, sizeof(P));
   P.tiles = b.S.tiles;
   P.ntiles = b.S.coloff + b.ncol_tot;
-  split_columns(b.g, true, std::sqrt(b.B.E[b.nb]), P);
+  split_columns(b.g, true, std::sqrt(b.B.E[b.nb]), b.mode == XI ? std::sqrt(b.B.E[b.nb]) : b.pimax,
+                (double)b.npts_tot / std::max(1, pl.nmock),
+                (b.prec == F64 ? 2.0 : 1.0) * (b.mode == WP ? 2.5 : 1.0), P);
   P.geom1 = b.d_geom;
   P.geom2 = b.d_geom;
   P.pos1 = b.S.pos;
