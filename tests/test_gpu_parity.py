@@ -175,6 +175,35 @@ def test_refine_factors(native, refine):
         _check(g, refw)
 
 
+@pytest.mark.parametrize("rmax,refine,expect_r", [
+    (120.0, (1, 1, 1), (1, 1, 1)),     # 3 cells per axis: exactly 2 r + 1
+    (150.0, (2, 2, 2), (2, 2, 2)),     # 5 cells per axis: exactly 2 r + 1
+    (150.0, (2, 1, 3), (2, 0, 3)),     # 5 cells, one wrapped cell, 8 cells
+])
+def test_minimal_periodic_grids(native, rmax, refine, expect_r):
+    """Periodic grids at the edge of the no-aliasing condition (an axis with
+    exactly 2 r + 1 cells, where the neighbour offsets -r..r reach every cell
+    of the axis once), mixed with a single wrapped cell: the auto-count's
+    half-shell must still meet every pair of cells once, and the cross count
+    every pair."""
+    a = synth.clustered(3_000, 60, 2.0, 420.0, seed=41, weights=True)
+    b = synth.uniform(2_000, 420.0, seed=42, weights=True)
+    edges = synth.log_edges(1.0, rmax, 8)
+    da, db = native.to_device(a), native.to_device(b)
+    for prec in ("fp64", "fp32"):
+        _say("minimal grid", rmax, refine, prec)
+        g = native.countpairs_xi(da, edges, precision=prec, periodic=True, boxsize=420.0,
+                                 refine=refine, need_ravg=True)
+        assert tuple(g.stats["refine"]) == expect_r
+        _check(g, oracle.xi(a, edges, periodic=True, box=420.0), weighted=True)
+        g = native.countpairs_wp(da, edges, 60.0, 6, precision=prec, periodic=True,
+                                 boxsize=420.0, refine=refine)
+        _check(g, oracle.wp(a, edges, 60.0, 6, periodic=True, box=420.0))
+        g = native.countpairs_cross(da, db, edges, precision=prec, periodic=True, boxsize=420.0,
+                                    refine=refine)
+        _check(g, oracle.xi(a, edges, periodic=True, box=420.0, other=b))
+
+
 @pytest.mark.parametrize("rmax", [80.0, 100.0])
 def test_large_rmax(native, rmax):
     """R_max of 80 and 100 in a box of 420 (the top of the paper's R_max
