@@ -175,6 +175,27 @@ def test_refine_factors(native, refine):
         _check(g, refw)
 
 
+@pytest.mark.parametrize("refine", [(1, 1, 1), (2, 2, 2), (3, 1, 2)])
+def test_nonperiodic_auto(native, refine):
+    """Auto-counts without periodic wrap: the half-shell meets the edges of
+    the catalogue's bounding box (columns and cells beyond it are skipped),
+    on a clustered catalogue stretched to a non-cubic region."""
+    c = synth.clustered(8_000, 200, 2.0, 200.0, seed=51, weights=True)
+    cat = synth.Catalog(c.x - 20.0, c.y * 0.75 + 5.0, c.z * 0.5, c.w)
+    edges = synth.log_edges(0.5, 20.0, 10)
+    d = native.to_device(cat)
+    ref = oracle.xi(cat, edges, periodic=False)
+    refw = oracle.wp(cat, edges, 15.0, 5, periodic=False)
+    for prec in ("fp64", "fp32"):
+        _say("nonperiodic auto", refine, prec)
+        g = native.countpairs_xi(d, edges, precision=prec, periodic=False, refine=refine,
+                                 need_ravg=True)
+        _check(g, ref, weighted=True)
+        g = native.countpairs_wp(d, edges, 15.0, 5, precision=prec, periodic=False,
+                                 refine=refine)
+        _check(g, refw)
+
+
 @pytest.mark.parametrize("rmax,refine,expect_r", [
     (120.0, (1, 1, 1), (1, 1, 1)),     # 3 cells per axis: exactly 2 r + 1
     (150.0, (2, 2, 2), (2, 2, 2)),     # 5 cells per axis: exactly 2 r + 1
