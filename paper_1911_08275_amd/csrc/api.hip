@@ -564,8 +564,22 @@ static int launch_pairs_t(hipStream_t st, const PairParams &P, size_t lds, int n
       return fail(CP_ERR_DEVICE, "cannot raise the LDS limit of the pair kernel");
     set_lds = lds;
   }
-  const int per_cu = std::max(1, std::min(8, (int)(160 * 1024 / std::max<size_t>(lds, 1))));
-  const int grid = num_cus() * per_cu;
+  // exactly the workgroups the CUs hold at once (registers, LDS and waves, as
+  // the runtime computes them for this kernel): a surplus would only start
+  // once the queues were drained and then probe every queue head, adding
+  // device-scope atomics to the end of the launch
+  static thread_local size_t occ_lds = ~(size_t)0;
+  static thread_local int occ_nw = 0, occ_per_cu = 0;
+  if (occ_lds != lds || occ_nw != nwaves) {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kern, 64 * nwaves, lds) != hipSuccess ||
+        n < 1)
+      n = std::max(1, std::min(8, (int)(160 * 1024 / std::max<size_t>(lds, 1))));
+    occ_lds = lds;
+    occ_nw = nwaves;
+    occ_per_cu = n;
+  }
+  const int grid = num_cus() * occ_per_cu;
   (void)hipGetLastError();  // drop any stale error so the check below is about this launch
   hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * nwaves), lds, st, P);
   const hipError_t e = hipGetLastError();
