@@ -158,8 +158,11 @@ def test_full_box_total(native):
         assert int(g.npairs.sum()) == cat.n * (cat.n - 1)
 
 
-@pytest.mark.parametrize("refine", [(1, 1, 1), (2, 2, 2), (3, 3, 3), (3, 3, 1), (1, 2, 4)])
+@pytest.mark.parametrize("refine", [(1, 1, 1), (2, 2, 2), (3, 3, 3), (3, 3, 1), (1, 2, 4), (8, 8, 8), (8, 1, 3)])
 def test_refine_factors(native, refine):
+    """Refine factors up to the cap of 8 cells per R_max (a half-shell of 145
+    neighbour columns at (8, 8, 8), cut into the most chunks a tile may have),
+    anisotropic ones included."""
     cat = synth.clustered(40_000, 800, 1.5, 420.0, seed=5)
     edges = synth.log_edges(0.1, 25.0, 14)
     _say("refine", refine)
