@@ -252,7 +252,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the pair counts "
-              "of this workload fit one MI355X and multi-GPU runs are not part of this build.",
+              "of this workload fit one MI355X and the library has no multi-GPU path.",
               file=sys.stderr)
         sys.exit(2)
 
