@@ -114,11 +114,19 @@ __global__ __launch_bounds__(1024) void k_scan_segments(const int *in, int *out,
   __shared__ int wsum[16];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   int carry = 0;
+  // the next tile's values are loaded before this tile's barriers, so the
+  // memory latency overlaps the scan
+  int nv[4];
+#pragma unroll
+  for (int k = 0; k < 4; k++) nv[k] = 4 * (int64_t)tid + k < S.len ? src[4 * tid + k] : 0;
   for (int64_t t0 = 0; t0 < S.len; t0 += 4096) {
     const int64_t i0 = t0 + 4 * (int64_t)tid;
     int v[4];
 #pragma unroll
-    for (int k = 0; k < 4; k++) v[k] = i0 + k < S.len ? src[i0 + k] : 0;
+    for (int k = 0; k < 4; k++) v[k] = nv[k];
+    const int64_t n0 = i0 + 4096;
+#pragma unroll
+    for (int k = 0; k < 4; k++) nv[k] = n0 + k < S.len ? src[n0 + k] : 0;
     const int loc = (v[0] + v[1]) + (v[2] + v[3]);
     int x = loc;
 #pragma unroll
