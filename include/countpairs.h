@@ -112,6 +112,11 @@ typedef struct {
   float ms_grid;             /* device time of the cell build (ms) */
   float ms_pairs;            /* device time of the pair kernel (ms) */
   float ms_total;            /* device time of the whole call (ms) */
+  int precision;             /* CP_PREC_* the pair kernel actually ran: a grid
+                                with a single wrapped cell on some axis (box
+                                under three cells of reach) takes per-pair
+                                minimum images and runs in binary64 whatever
+                                was asked for */
 } cp_stats;
 
 /* Fill *o with defaults: FP32 recheck, non-periodic, refine 0 (library
@@ -185,9 +190,11 @@ int countpairs_last_stats(cp_stats *out);
  *                    xi_edges / wp_edges may be NULL to skip that statistic;
  *                    o: precision, refine, periodic (must be 1) and boxsize.
  *   cp_plan_execute  enqueue one evaluation on stream (asynchronous).
- *   cp_plan_results  synchronise and copy counts: xi_npairs nmocks*(xi_nedges-1),
- *                    wp_npairs nmocks*(wp_nedges-1)*npibins (either may be NULL);
- *                    auto-counts follow o->count_mode.
+ *   cp_plan_results  synchronise the stream of the last execute and copy counts:
+ *                    xi_npairs nmocks*(xi_nedges-1), wp_npairs
+ *                    nmocks*(wp_nedges-1)*npibins (either may be NULL);
+ *                    auto-counts follow o->count_mode.  CP_ERR_INTERNAL when a
+ *                    work queue was not drained (the counts would be short).
  *   cp_plan_destroy  free everything (NULL is fine).
  */
 typedef struct cp_plan cp_plan;

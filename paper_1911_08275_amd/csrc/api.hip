@@ -698,6 +698,7 @@ static int run(const Call &c, uint64_t *npairs, double *wsum, double *ravg) {
   }
   if (p1.n + (autoc ? 0 : p2.n) == 0) {
     memset(&g_stats, 0, sizeof(g_stats));
+    g_stats.precision = o.precision;
     g_stats_valid = true;
     return CP_OK;
   }
@@ -1013,6 +1014,7 @@ static int run(const Call &c, uint64_t *npairs, double *wsum, double *ravg) {
   (void)hipEventElapsedTime(&g_stats.ms_grid, ev[0], ev[1]);
   (void)hipEventElapsedTime(&g_stats.ms_pairs, ev[1], ev[2]);
   (void)hipEventElapsedTime(&g_stats.ms_total, ev[0], ev[3]);
+  g_stats.precision = prec == F32R ? CP_PREC_FP32_RECHECK : CP_PREC_FP64;
   g_stats_valid = true;
   return CP_OK;
 }
@@ -1176,6 +1178,7 @@ struct cp_plan {
   int noprune = 0;
   void *mem = nullptr;
   hipStream_t cap = nullptr;
+  hipStream_t last = nullptr;    // stream of the last execute (results and stats sync it)
   hipGraphExec_t gexec = nullptr;
   bool use_graph = true;
   int timed = 0;                 // 1: eager events, 2: graph events
@@ -1476,6 +1479,7 @@ int cp_plan_create(const cp_points *mocks, int nmocks, const double *xi_edges, i
 int cp_plan_execute(cp_plan *pl, void *stream) {
   if (!pl) return fail(CP_ERR_INVALID_ARG, "plan is NULL");
   hipStream_t st = (hipStream_t)stream;
+  pl->last = st;
   if (!pl->use_graph) {
     pl->timed = 1;
     return plan_enqueue(*pl, st, true);
@@ -1508,7 +1512,7 @@ int cp_plan_execute(cp_plan *pl, void *stream) {
 
 int cp_plan_results(cp_plan *pl, uint64_t *xi_npairs, uint64_t *wp_npairs) {
   if (!pl) return fail(CP_ERR_INVALID_ARG, "plan is NULL");
-  HIPCHK(hipDeviceSynchronize());
+  HIPCHK(hipStreamSynchronize(pl->last));
   int flags = 0;
   const double mult = pl->count_mode == CP_ORDERED ? 2 : 1;
   for (int s = 0; s < 2; s++) {
@@ -1518,6 +1522,17 @@ int cp_plan_results(cp_plan *pl, uint64_t *xi_npairs, uint64_t *wp_npairs) {
     int f = 0;
     HIPCHK(hipMemcpy(&f, b.d_err, sizeof(int), hipMemcpyDeviceToHost));
     flags |= f;
+    if (f) continue;
+    // every queue item must have been taken (as for single calls)
+    std::vector<unsigned long long> st(kStatWords);
+    HIPCHK(hipMemcpy(st.data(), b.d_stats, sizeof(unsigned long long) * kStatWords,
+                     hipMemcpyDeviceToHost));
+    const int64_t nitems = (int64_t)st[4] * b.P.nsplit;
+    for (int k = 0; k < kQueues; k++) {
+      const int64_t len = nitems * (k + 1) / kQueues - nitems * k / kQueues;
+      if (st[5 + (size_t)k * kQStride] < (unsigned long long)len)
+        return fail(CP_ERR_INTERNAL, "work queue not drained");
+    }
     if (!out) continue;
     std::vector<unsigned long long> h((size_t)b.nout * pl->nmock);
     HIPCHK(hipMemcpy(h.data(), b.d_hist, 8 * h.size(), hipMemcpyDeviceToHost));
@@ -1532,7 +1547,7 @@ int cp_plan_results(cp_plan *pl, uint64_t *xi_npairs, uint64_t *wp_npairs) {
 
 int cp_plan_stats(cp_plan *pl, cp_stats *xs, cp_stats *ws) {
   if (!pl) return fail(CP_ERR_INVALID_ARG, "plan is NULL");
-  HIPCHK(hipDeviceSynchronize());
+  HIPCHK(hipStreamSynchronize(pl->last));
   for (int s = 0; s < 2; s++) {
     Batch &b = s ? pl->wp : pl->xi;
     cp_stats *o = s ? ws : xs;
@@ -1548,6 +1563,7 @@ int cp_plan_stats(cp_plan *pl, cp_stats *xs, cp_stats *ws) {
     o->cell_pairs = st[2];
     o->cell_pairs_pruned = st[3];
     o->tiles = nt;
+    o->precision = b.prec == F32R ? CP_PREC_FP32_RECHECK : CP_PREC_FP64;
     for (int a = 0; a < 3; a++) {
       o->grid[a] = b.g.n[a];
       o->refine[a] = b.g.r[a];

@@ -52,14 +52,17 @@ class cp_stats(ctypes.Structure):
                 ("cell_pairs", ctypes.c_uint64), ("cell_pairs_pruned", ctypes.c_uint64),
                 ("tiles", ctypes.c_uint64), ("grid", ctypes.c_int * 3),
                 ("refine", ctypes.c_int * 3), ("ms_grid", ctypes.c_float),
-                ("ms_pairs", ctypes.c_float), ("ms_total", ctypes.c_float)]
+                ("ms_pairs", ctypes.c_float), ("ms_total", ctypes.c_float),
+                ("precision", ctypes.c_int)]
 
     def todict(self) -> dict:
         return dict(candidates=int(self.candidates), rechecks=int(self.rechecks),
                     cell_pairs=int(self.cell_pairs), cell_pairs_pruned=int(self.cell_pairs_pruned),
                     tiles=int(self.tiles), grid=list(self.grid), refine=list(self.refine),
                     ms_grid=float(self.ms_grid), ms_pairs=float(self.ms_pairs),
-                    ms_total=float(self.ms_total))
+                    ms_total=float(self.ms_total),
+                    precision={CP_PREC_FP64: "fp64",
+                               CP_PREC_FP32_RECHECK: "fp32"}.get(int(self.precision), "?"))
 
 
 class CountpairsError(RuntimeError):

@@ -42,6 +42,34 @@ def test_struct_layouts(native):
     assert ctypes.sizeof(native.cp_options) == 72
 
 
+def test_struct_layouts_match_header(native, tmp_path):
+    """sizeof and field offsets of the C structs, compiled from the header
+    with gcc, equal the ctypes mirrors of the binding."""
+    import subprocess
+    fields = {"cp_points": ["n", "x", "w", "dtype"],
+              "cp_options": ["precision", "boxsize", "refine", "stream", "workspace_bytes",
+                             "no_prune"],
+              "cp_stats": ["candidates", "tiles", "grid", "refine", "ms_grid", "ms_total",
+                           "precision"]}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "countpairs.h"',
+             'int main(void) {']
+    for st, fs in fields.items():
+        lines.append(f'printf("{st} %zu\\n", sizeof({st}));')
+        for f in fs:
+            lines.append(f'printf("{st}.{f} %zu\\n", offsetof({st}, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    out = dict(l.split() for l in subprocess.check_output([str(exe)]).decode().splitlines())
+    for st, fs in fields.items():
+        cls = getattr(native, st)
+        assert int(out[st]) == ctypes.sizeof(cls), st
+        for f in fs:
+            assert int(out[f"{st}.{f}"]) == getattr(cls, f).offset, (st, f)
+
+
 def test_rejects_bad_prune_flag(native):
     o = native.options()
     o.no_prune = 2
