@@ -95,10 +95,32 @@ static float bitsf(uint32_t b) {
 // at or above E_nb).  A cell holding more than one band boundary is marked
 // uncertain as a whole, which is always safe.
 
+// A fixed-capacity array: the binning set-up of a call runs without heap
+// allocation (the entry point without allocation relies on it).
+template <class T, int N> struct Fixed {
+  T v[N];
+  int n = 0;
+  void assign(int m, const T &x) {
+    n = m;
+    for (int i = 0; i < m; i++) v[i] = x;
+  }
+  void resize(int m) { n = m; }
+  int size() const { return n; }
+  bool empty() const { return n == 0; }
+  T *data() { return v; }
+  const T *data() const { return v; }
+  T &operator[](int i) { return v[i]; }
+  const T &operator[](int i) const { return v[i]; }
+};
+
+constexpr int kTabMax = 4096;   // decision-table cells
+
 struct Table {
-  std::vector<uint2> e;
+  Fixed<uint2, kTabMax> e;
   int lo = 0, hi = 0;
 };
+using EdgeF = Fixed<float, kMaxBins + 1>;
+using EdgeD = Fixed<double, kMaxBins + 1>;
 
 static const uint32_t kBig = 0x7E000000u;     // ~4.25e37, finite
 static const float kNegBig = -3.0e38f;
@@ -110,20 +132,19 @@ static uint32_t hi_with_k(float z, int k) {
   return b2;
 }
 
-static bool build_table(const std::vector<float> &C, const std::vector<float> &Av, int shift,
-                        Table &T) {
-  const int nt = (int)C.size();  // nb + 1 thresholds
+static bool build_table(const EdgeF &C, const EdgeF &Av, int shift, Table &T) {
+  const int nt = C.size();  // nb + 1 thresholds
   // merged uncertain zones
   struct Z {
     float lo, hi;
   };
-  std::vector<Z> zones;
+  Fixed<Z, kMaxBins + 1> zones;
   for (int k = 0; k < nt; k++) {
     if (!(Av[k] > C[k])) continue;
-    if (!zones.empty() && C[k] <= zones.back().hi)
-      zones.back().hi = std::max(zones.back().hi, Av[k]);
+    if (!zones.empty() && C[k] <= zones[zones.n - 1].hi)
+      zones[zones.n - 1].hi = std::max(zones[zones.n - 1].hi, Av[k]);
     else
-      zones.push_back({C[k], Av[k]});
+      zones[zones.n++] = {C[k], Av[k]};
   }
   auto sigma = [&](float v) {
     int s = 0;
@@ -139,24 +160,28 @@ static bool build_table(const std::vector<float> &C, const std::vector<float> &A
   if (!std::isfinite(minpos)) minpos = Av[nt - 1];
   T.lo = cell_of(minpos);
   T.hi = std::max(T.lo, cell_of(Av[nt - 1]));
-  if (T.hi - T.lo + 1 > 4096) return false;
+  if (T.hi - T.lo + 1 > kTabMax) return false;
   T.e.assign(T.hi - T.lo + 1, make_uint2(0, 0));
   for (int m = T.lo; m <= T.hi; m++) {
     const float vlo = m == T.lo ? -INFINITY : bitsf((uint32_t)m << shift);
     const float vhi = m == T.hi ? INFINITY : bitsf((uint32_t)(m + 1) << shift);
-    std::vector<Z> in;
-    for (const Z &z : zones)
-      if (z.hi > vlo && z.lo < vhi) in.push_back(z);
+    int nin = 0;          // zones meeting this cell, and the first of them
+    Z first{0.f, 0.f};
+    for (int q = 0; q < zones.size(); q++)
+      if (zones[q].hi > vlo && zones[q].lo < vhi) {
+        if (!nin) first = zones[q];
+        nin++;
+      }
     uint2 ent;
     const uint2 all_unc = make_uint2(fbits(kNegBig), kBig | 1u);
-    if (in.empty()) {
+    if (nin == 0) {
       const float rep = m == T.lo ? bitsf((uint32_t)m << shift) : vlo;
       const int s = sigma(rep);
       ent = make_uint2(kBig, kBig | (uint32_t)(s + 1));
-    } else if (in.size() > 1) {
+    } else if (nin > 1) {
       ent = all_unc;
     } else {
-      const Z z = in[0];
+      const Z z = first;
       const bool sin = z.lo > vlo, ein = z.hi < vhi;
       if (!sin && !ein) {
         ent = all_unc;
@@ -273,7 +298,8 @@ static void split_columns(const Geometry &g, bool autoc, double reach, double re
                           double npts2, double cost, PairParams &P) {
   const int rx = g.r[0], ry = g.r[1], ncy = 2 * ry + 1;
   const int ncols = autoc ? 1 + ry + rx * ncy : (2 * rx + 1) * ncy;
-  std::vector<double> cum(ncols + 1, 0.0);
+  Fixed<double, (2 * 8 + 1) * (2 * 8 + 1) + 1> cum;   // columns + 1 at refine 8 per axis
+  cum.assign(ncols + 1, 0.0);
   for (int c = 0; c < ncols; c++) {
     int ox, oy;
     if (autoc) {
@@ -591,10 +617,9 @@ static int launch_pairs_t(hipStream_t st, const PairParams &P, size_t lds, int n
 static int launch_pairs(hipStream_t st, int mode, int prec, int w, const PairParams &P,
                         size_t lds, int nwaves) {
   if (mode == XI) {
-    if (prec == F32R) {
-      if (w) return fail(CP_ERR_INTERNAL, "weighted xi runs in binary64");
-      return launch_pairs_t<XI, F32R, 0>(st, P, lds, nwaves);
-    }
+    if (prec == F32R)
+      return w ? launch_pairs_t<XI, F32R, 1>(st, P, lds, nwaves)
+               : launch_pairs_t<XI, F32R, 0>(st, P, lds, nwaves);
     return w ? launch_pairs_t<XI, F64, 1>(st, P, lds, nwaves)
              : launch_pairs_t<XI, F64, 0>(st, P, lds, nwaves);
   }
@@ -606,8 +631,8 @@ static int launch_pairs(hipStream_t st, int mode, int prec, int w, const PairPar
 
 // Binning setup shared by single calls and plans.
 struct Binning {
-  std::vector<double> E;
-  std::vector<float> C32, A32;
+  EdgeD E;
+  EdgeF C32, A32;
   Table t32, t64;
   int shift;
   float AB32;
@@ -624,7 +649,11 @@ static int make_binning(int mode, int prec, const double *edges, int nedges, dou
   for (int k = 0; k < nedges; k++) B.E[k] = edges[k] * edges[k];
   const double EB = B.E[nb];
   B.bnd = error_bounds(mode, g, EB, pimax, M);
-  std::vector<float> C32(nedges), A32(nedges), C64(nedges), A64(nedges);
+  EdgeF C32, A32, C64, A64;
+  C32.resize(nedges);
+  A32.resize(nedges);
+  C64.resize(nedges);
+  A64.resize(nedges);
   for (int k = 0; k < nedges; k++) {
     const double e = B.E[k];
     if (e == 0.0) {
@@ -705,14 +734,15 @@ static int run(const Call &c, uint64_t *npairs, double *wsum, double *ravg) {
   const bool weighted = o.need_ravg != 0;
   const double rmax = c.edges[nb];
 
-  hipEvent_t ev[4];
-  for (auto &e : ev) HIPCHK(hipEventCreate(&e));
+  hipEvent_t ev[4] = {};
   struct EvGuard {
     hipEvent_t *e;
     ~EvGuard() {
-      for (int i = 0; i < 4; i++) (void)hipEventDestroy(e[i]);
+      for (int i = 0; i < 4; i++)
+        if (e[i]) (void)hipEventDestroy(e[i]);
     }
   } evg{ev};
+  for (auto &e : ev) HIPCHK(hipEventCreate(&e));
   HIPCHK(hipEventRecord(ev[0], st));
 
   PointsDev pd[2];
@@ -783,11 +813,6 @@ static int run(const Call &c, uint64_t *npairs, double *wsum, double *ravg) {
                                o.refine, ntot);
   int prec = o.precision == CP_PREC_FP32_RECHECK ? F32R : F64;
   if (g.wrap[0] || g.wrap[1] || g.wrap[2]) prec = F64;   // per-pair minimum image: binary64
-  // Weighted xi needs the binary64 separation of every counted pair for the
-  // weighted mean, and binary64 FMAs issue at the binary32 rate on gfx950,
-  // so a binary32 filter would only add work: the binary64 loops run (same
-  // counts by definition).
-  if (c.mode == XI && o.need_ravg) prec = F64;
   double M = 0;
   for (int a = 0; a < 3; a++) M = std::max(M, std::fabs(g.lo[a]) + g.ext[a]);
   if (o.periodic) M = std::max(M, o.boxsize);
@@ -874,9 +899,13 @@ static int run(const Call &c, uint64_t *npairs, double *wsum, double *ravg) {
     // the small records and tables are carved consecutively: one upload
     char *up0 = (char *)d_sm;
     const size_t upn = (size_t)((char *)(d_a32 + c.nedges) - up0);
-    std::vector<char> hup(upn, 0);
+    // tables of at most kTabMax cells each, 256-byte aligned pieces
+    constexpr size_t kUpMax = sizeof(Smalls) + 2 * 8 * kTabMax + 16 * (kMaxBins + 1) + 8 * 256;
+    if (upn > kUpMax) return fail(CP_ERR_INTERNAL, "upload block larger than expected");
+    alignas(16) char hup[kUpMax];
+    memset(hup, 0, upn);
     auto put = [&](const void *dev, const void *src, size_t bytes) {
-      if (bytes) memcpy(hup.data() + ((const char *)dev - up0), src, bytes);
+      if (bytes) memcpy(hup + ((const char *)dev - up0), src, bytes);
     };
     put(d_sm, &hs, sizeof(hs));
     put(d_t32, B.t32.e.data(), (size_t)n32 * 8);
@@ -884,7 +913,7 @@ static int run(const Call &c, uint64_t *npairs, double *wsum, double *ravg) {
     put(d_E, B.E.data(), (size_t)c.nedges * 8);
     put(d_c32, B.C32.data(), (size_t)c.nedges * 4);
     put(d_a32, B.A32.data(), (size_t)c.nedges * 4);
-    HIPCHK(hipMemcpyAsync(up0, hup.data(), upn, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(up0, hup, upn, hipMemcpyHostToDevice, st));
   }
   {
     // histogram, weight sums, statistics and error flag are carved
@@ -960,45 +989,63 @@ static int run(const Call &c, uint64_t *npairs, double *wsum, double *ravg) {
   if ((rc = launch_pairs(st, c.mode, prec, weighted, P, lds, nwaves))) return rc;
   HIPCHK(hipEventRecord(ev[2], st));
 
-  // ---- results: histogram, weight sums, statistics and the error flag are
-  // carved consecutively, so one download brings them all
-  std::vector<unsigned long long> h(nout);
-  std::vector<double> hwv(nout), hwrv(nout);
+  // ---- results
   unsigned long long hst[kStatWords];
   int eflag = 0;
-  char *dn0 = (char *)d_hist;
-  const size_t dnn = (size_t)((char *)(d_err + 1) - dn0);
-  std::vector<char> hdn(dnn);
-  HIPCHK(hipMemcpyAsync(hdn.data(), dn0, dnn, hipMemcpyDeviceToHost, st));
-  HIPCHK(hipEventRecord(ev[3], st));
-  HIPCHK(hipStreamSynchronize(st));
-  auto get = [&](void *dst, const void *dev, size_t bytes) {
-    memcpy(dst, hdn.data() + ((const char *)dev - dn0), bytes);
-  };
-  get(h.data(), d_hist, 8 * (size_t)nout);
-  if (weighted) {
-    get(hwv.data(), d_hw, 8 * (size_t)nout);
-    get(hwrv.data(), d_hwr, 8 * (size_t)nout);
-  }
-  get(hst, d_stats, sizeof(hst));
-  get(&eflag, d_err, sizeof(int));
-  const int ntiles = (int)hst[4];
-  if ((rc = map_err_flags(eflag))) return rc;
+  std::vector<unsigned long long> h;
+  std::vector<double> hwv, hwrv;
   {
+    // histogram, weight sums, statistics and the error flag are carved
+    // consecutively, so one download brings them all
+    h.resize(nout);
+    hwv.resize(nout);
+    hwrv.resize(nout);
+    char *dn0 = (char *)d_hist;
+    const size_t dnn = (size_t)((char *)(d_err + 1) - dn0);
+    std::vector<char> hdn(dnn);
+    HIPCHK(hipMemcpyAsync(hdn.data(), dn0, dnn, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipEventRecord(ev[3], st));
+    HIPCHK(hipStreamSynchronize(st));
+    auto get = [&](void *dst, const void *dev, size_t bytes) {
+      memcpy(dst, hdn.data() + ((const char *)dev - dn0), bytes);
+    };
+    get(h.data(), d_hist, 8 * (size_t)nout);
+    if (weighted) {
+      get(hwv.data(), d_hw, 8 * (size_t)nout);
+      get(hwrv.data(), d_hwr, 8 * (size_t)nout);
+    }
+    get(hst, d_stats, sizeof(hst));
+    get(&eflag, d_err, sizeof(int));
+  }
+  const int ntiles = (int)hst[4];
+  rc = map_err_flags(eflag);
+  if (!rc) {
     const int64_t nitems = (int64_t)ntiles * P.nsplit;
     for (int k = 0; k < kQueues; k++) {
       const int64_t len = nitems * (k + 1) / kQueues - nitems * k / kQueues;
       if (hst[5 + k * kQStride] < (unsigned long long)len)
-        return fail(CP_ERR_INTERNAL, "work queue not drained");
+        rc = fail(CP_ERR_INTERNAL, "work queue not drained");
     }
+  }
+  if (rc) {
+    // failed calls leave zero outputs
+    memset(npairs, 0, sizeof(uint64_t) * nout);
+    if (o.need_ravg) {
+      memset(wsum, 0, sizeof(double) * nout);
+      memset(ravg, 0, sizeof(double) * nout);
+    }
+    return rc;
   }
 
   const double mult = (autoc && o.count_mode == CP_ORDERED) ? 2.0 : 1.0;
   for (int k = 0; k < nout; k++) {
-    npairs[k] = (uint64_t)h[k] * (uint64_t)mult;
+    const unsigned long long hk = h[k];
+    const double w = hwv[k];
+    const double wr = hwrv[k];
+    npairs[k] = (uint64_t)hk * (uint64_t)mult;
     if (weighted) {
-      wsum[k] = hwv[k] * mult;
-      ravg[k] = h[k] ? hwrv[k] / hwv[k] : 0.0;
+      wsum[k] = w * mult;
+      ravg[k] = hk ? wr / w : 0.0;
     }
   }
   memset(&g_stats, 0, sizeof(g_stats));

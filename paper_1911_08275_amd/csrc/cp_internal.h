@@ -157,14 +157,28 @@ __host__ __device__ inline int cell_coord(const GridGeom &g, int a, double v) {
 __host__ __device__ inline size_t align16(size_t v) { return (v + 15) & ~(size_t)15; }
 
 struct LdsLayout {
-  size_t tab32, tab64, E, common, wave_hist, wave_w, wave_bytes;
+  size_t tab32, tab64, E, common, wave_hist, wave_w, wave_list, wave_bytes;
 };
+
+// Weighted xi with the binary32 filter: the filter needs no decision table
+// (it only tests s~ against the band above E_B), and every pair it passes
+// goes to a per-wave list of (tile lane, record) pairs that is evaluated in
+// binary64, 64 pairs at a time.
+__host__ __device__ constexpr bool xi_f32_weighted(int mode, int prec, int weighted) {
+  return mode == XI && prec == F32R && weighted;
+}
+// List entries per wave: fewer than 64 are left over after a drain, and a
+// group of four records adds at most 4 x 64; then one dummy entry per lane,
+// written by lanes that keep nothing (the append has no branch).
+constexpr int kListCap = 64 + 4 * 64;
+constexpr int kListWords = kListCap + 64;
 
 __host__ __device__ inline LdsLayout lds_layout(int mode, int prec, int weighted, int n32, int n64,
                                                int nb, int npi) {
   LdsLayout L;
   size_t off = 0;
   L.tab32 = off;
+  if (xi_f32_weighted(mode, prec, weighted)) n32 = 0;
   off += (size_t)(prec == F32R ? n32 : 0) * 8;
   L.tab64 = off;
   off += (size_t)n64 * 8;
@@ -176,7 +190,8 @@ __host__ __device__ inline LdsLayout lds_layout(int mode, int prec, int weighted
   L.wave_hist = align16(words * 4);
   // weight sums are shared by the wave (one row of slots), not lane-private
   L.wave_w = weighted ? (mode == XI ? (size_t)NS * kWStripe : words) * 8 : 0;
-  L.wave_bytes = L.wave_hist + 2 * L.wave_w;
+  L.wave_list = L.wave_hist + 2 * L.wave_w;
+  L.wave_bytes = L.wave_list + (xi_f32_weighted(mode, prec, weighted) ? (size_t)kListWords * 4 : 0);
   return L;
 }
 

@@ -36,6 +36,7 @@
 #include "cp_internal.h"
 
 #include <float.h>
+#include <type_traits>
 
 namespace cp {
 
@@ -163,6 +164,7 @@ __device__ inline void add_w(double *p, double w, double wr) {
 struct WaveArea {
   uint32_t *hist;
   double *hw;   // weight sums, interleaved: hw[2 i] = sum w, hw[2 i + 1] = sum w r
+  uint32_t *list;   // weighted xi, binary32 mode: (tile lane, record) pairs to evaluate
 };
 
 template <int MODE, int W>
@@ -648,6 +650,182 @@ __device__ inline void loop_wp_f32_w(const PairParams &P, WaveArea A, const Lane
            });
 }
 
+// Waits for every scalar load and LDS operation issued so far (s_waitcnt
+// lgkmcnt(0)).  Scalar loads complete out of order, so before a group of
+// streamed records is used the compiler waits for all of them; issuing the
+// look-ahead load of the next group only after this wait lets it overlap the
+// work on the current group.
+__device__ inline void wait_lgkm() { __builtin_amdgcn_s_waitcnt(0xC07F); }
+
+// Weighted xi, binary32 filter with compaction, for units whose separation
+// range reaches E_B (or lies below E_0).  The weighted mean needs the
+// binary64 separation of every counted pair.  Evaluated for every candidate
+// on the wave, that binary64 work runs on every record where any lane is in
+// range, although most candidates of such units are not.  Here the binary32
+// Gram form s~ screens every candidate: a pair with s~ >= AB32 (= up(E_B +
+// eps), so its binary64 s is at or beyond E_B) is dropped, every other pair is
+// appended to the wave's list.  The list is evaluated 64 pairs at a time, one
+// pair per lane: the canonical binary64 separation decides the bin (so the
+// counts are those of the binary64 definition by construction; the screen
+// only removes pairs that the definition drops), and the same value gives
+// sqrt(s) for the weighted sums.  A batch's binary64 records are loaded after
+// one group of records and evaluated after the next, so the loads overlap
+// the screening.  nrechk counts the listed pairs that binary64 places at or
+// beyond E_B.
+//   CLS 1: slots [nb, nb + 1]: every kept pair lies in the last bin.
+//   CLS 2: slots [nb - 1, nb + 1]: one compare against E_{nb-1}.
+//   CLS 0: any other range: decision table, counts and sums in LDS.
+// SH: the unit has a periodic shift (added to each binary64 difference).
+// A list entry holds byte offsets: (record << 11) | (tile lane << 5), so the
+// unit may have at most 2^21 records.  Records go four at a time; the list
+// holds at most 63 + 4 x 64 entries, and lanes that keep nothing write a
+// dummy entry of their own, so the append needs no branch.  The look-ahead
+// may read up to 7 records past the unit (the stream arrays are padded past
+// their end); the last group masks the records past the unit.
+// exec = all lanes: list entries go to lanes regardless of the tile's size.
+template <int CLS, bool SH>
+__device__ inline void loop_xi_f32_w(const PairParams &P, WaveArea A, int lane, float rx,
+                                     float ry, float rz, float ra, const Unit &U,
+                                     const double4 *tpts, const uint2 *tab64, const double *sE,
+                                     uint32_t &nrechk) {
+  const int nb = P.nb;
+  const float AB = P.AB32;
+  const double EB = P.EB;
+  const double Em = sE[nb > 1 ? nb - 1 : nb];
+  const int st = lane & (kWStripe - 1);
+  uint32_t *list = A.list;
+  const char *pos = (const char *)(U.pos + U.jb);
+  const char *tp = (const char *)tpts;
+  const int nrec = U.je - U.jb;
+  const uint32_t lane32 = (uint32_t)lane << 5;
+  uint32_t c1 = 0, c2 = 0, nout = 0;
+  double w1 = 0, r1 = 0, w2 = 0, r2 = 0;   // last bin (w1, r1); CLS 2 also bin nb - 2
+  int head = 0, tail = 0;                   // wave-uniform: pending entries list[head, tail)
+  int listed = 0;                           // wave-uniform: pairs evaluated in binary64
+  int pn = 0;                               // lanes of the batch in flight (0: none)
+  double4 pq = make_double4(0, 0, 0, 0), pt = pq;
+  auto issue = [&](int n) {
+    const uint32_t e = list[head + lane];
+    // idle lanes read tile point 0 and record 0 (a short last tile has no
+    // point 63, and stale entries may name any record)
+    const bool v = lane < n;
+    const uint32_t toff = v ? (e & 0x7E0u) : 0u;
+    const uint32_t joff = v ? ((e >> 6) & ~31u) : 0u;
+    pq = *(const double4 *)(pos + joff);
+    pt = *(const double4 *)(tp + toff);
+    pn = n;
+    listed += n;
+    head += 64;
+  };
+  // FULL: all 64 lanes hold a pair
+  auto finish = [&](auto full) {
+    constexpr bool FULL = decltype(full)::value;
+    const bool v = FULL || lane < pn;
+    double dx = pq.x - pt.x, dy = pq.y - pt.y, dz = pq.z - pt.z;
+    if (SH) {
+      dx = dx + U.S[0];
+      dy = dy + U.S[1];
+      dz = dz + U.S[2];
+    }
+    const double s = (dx * dx + dy * dy) + dz * dz;
+    const double r = sep_sqrt(s);
+    if (CLS == 0) {
+      if (v) {
+        const int slot = slot64(tab64, P.tab64_lo, P.tab64_hi, P.tab_shift, sE, nb, s);
+        const double ww = pt.w * pq.w;
+        atomicAdd(&A.hist[slot * 64 + lane], 1u);
+        add_w(A.hw + 2 * (slot * kWStripe + st), ww, ww * r);
+        nout += slot > nb ? 1u : 0u;
+      }
+    } else {
+      const bool in = v && s < EB;
+      const double ww = in ? pt.w * pq.w : 0.0;
+      if (CLS == 1) {
+        c1 += in ? 1u : 0u;
+        w1 += ww;
+        r1 = __builtin_fma(ww, r, r1);
+      } else {
+        const bool hi = s >= Em;
+        const double a = hi ? ww : 0.0;
+        const double b = ww - a;   // exact: ww or 0
+        c1 += (in && hi) ? 1u : 0u;
+        c2 += (in && !hi) ? 1u : 0u;
+        w1 += a;
+        r1 = __builtin_fma(a, r, r1);
+        w2 += b;
+        r2 = __builtin_fma(b, r, r2);
+      }
+    }
+    pn = 0;
+  };
+  // full batches: evaluate the one in flight, load the next; the fewer than
+  // 64 entries left over move to the front of the list
+  auto service = [&]() {
+    __builtin_amdgcn_wave_barrier();
+    if (tail - head >= 64) {
+      do {
+        if (pn) finish(std::true_type());
+        issue(64);
+      } while (tail - head >= 64);
+      const uint32_t rest = list[min(head + lane, kListCap - 1)];
+      __builtin_amdgcn_wave_barrier();
+      if (lane < tail - head) list[lane] = rest;
+      tail -= head;
+      head = 0;
+    }
+    __builtin_amdgcn_wave_barrier();
+  };
+  auto screen = [&](int jr, bool check, float qx, float qy, float qz, float qw) {
+    const float d = gram3(rx, ry, rz, ra, qx, qy, qz, qw);
+    const bool keep = d < AB && (!check || jr < nrec);
+    const unsigned long long m = __builtin_amdgcn_ballot_w64(keep);
+    const uint32_t at = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+    list[keep ? (uint32_t)tail + at : (uint32_t)(kListCap + lane)] = ((uint32_t)jr << 11) | lane32;
+    tail += (int)__popcll(m);
+  };
+  sfloat *p = (sfloat *)(U.strm + U.jb);
+  float a[16];
+  CP_LOAD16(a, p);
+  for (int jr = 0; jr < nrec; jr += 4) {
+    wait_lgkm();
+    service();
+    float b[16];
+    CP_LOAD16(b, p + 16);
+    if (jr + 4 <= nrec) {
+#pragma unroll
+      for (int u = 0; u < 4; u++)
+        screen(jr + u, false, a[4 * u], a[4 * u + 1], a[4 * u + 2], a[4 * u + 3]);
+    } else {
+#pragma unroll
+      for (int u = 0; u < 4; u++)
+        screen(jr + u, true, a[4 * u], a[4 * u + 1], a[4 * u + 2], a[4 * u + 3]);
+    }
+#pragma unroll
+    for (int t = 0; t < 16; t++) a[t] = b[t];
+    p += 16;
+  }
+  service();
+  if (pn) finish(std::true_type());
+  if (tail > head) {
+    issue(tail - head);
+    finish(std::false_type());
+  }
+  if (CLS == 0) {
+    nrechk += nout;
+  } else {
+    // listed pairs that binary64 placed at or beyond E_B
+    const unsigned long long kept = wave_sum_u64((unsigned long long)(c1 + c2));
+    if (lane == 0) nrechk += (uint32_t)(listed - (int)kept);
+    atomicAdd(&A.hist[nb * 64 + lane], c1);
+    add_w(A.hw + 2 * (nb * kWStripe + st), w1, r1);
+  }
+  if (CLS == 2 && nb > 1) {
+    atomicAdd(&A.hist[(nb - 1) * 64 + lane], c2);
+    add_w(A.hw + 2 * ((nb - 1) * kWStripe + st), w2, r2);
+  }
+}
+
 // ---------------------------------------------------------------- FP64 loops
 
 // xi, binary64, two-slot unit: one exact compare per pair.  exec = valid lanes.
@@ -809,10 +987,16 @@ __device__ inline void loop_f64(const PairParams &P, WaveArea A, const LanePt &L
 
 // ------------------------------------------------------------------ kernel
 
-// Weighted xi always runs in binary64 (the host routes it there), so
-// <XI, F32R, 1> is not instantiated.
+// Waves per SIMD the register allocation aims at: five (96 VGPRs) for most
+// instances; weighted xi with the binary32 filter holds a pair list per wave
+// and fits four workgroups per CU in LDS, so it takes the 128 VGPRs of four.
+template <int MODE, int PREC, int W> struct PairOcc {
+  static constexpr int waves = xi_f32_weighted(MODE, PREC, W) ? 4 : 5;
+};
+
 template <int MODE, int PREC, int W>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_pairs(PairParams P) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PairOcc<MODE, PREC, W>::waves)))
+void k_pairs(PairParams P) {
   extern __shared__ __align__(16) unsigned char smem[];
   // bit k: a wave of this workgroup found queue k drained.  Queues only
   // drain, so the other waves skip it without another device-scope atomic:
@@ -823,7 +1007,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
   if (threadIdx.x == 0) qdrained = 0u;
   const int lane = threadIdx.x & 63;
   const int wid = threadIdx.x >> 6;
-  const int n32 = PREC == F32R ? P.tab32_hi - P.tab32_lo + 1 : 0;
+  const int n32 = (PREC == F32R && !xi_f32_weighted(MODE, PREC, W)) ? P.tab32_hi - P.tab32_lo + 1 : 0;
   const int n64 = P.tab64_hi - P.tab64_lo + 1;
   const LdsLayout LY = lds_layout(MODE, PREC, W, n32, n64, P.nb, P.npi);
   uint2 *tab32 = (uint2 *)(smem + LY.tab32);
@@ -836,6 +1020,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
   WaveArea A;
   A.hist = (uint32_t *)wb;
   A.hw = (double *)(wb + LY.wave_hist);
+  A.list = (uint32_t *)(wb + LY.wave_list);
   const int NS = P.nslots;
   const int hwords = MODE == XI ? NS * 64 : NS * P.npi;
   const int wwords = MODE == XI ? NS * kWStripe : hwords;
@@ -1082,7 +1267,32 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
         }
         st_cand += (unsigned long long)nvalid * nj;
         const bool two = MODE == XI && !own && !anywrap && U.slot_hi == U.slot_lo + 1;
-        if (PREC == F32R && !anywrap) {
+        // weighted xi in binary32 mode: units with every pair in [E_0, E_B)
+        // need the binary64 separation of every pair anyway (binary64 loops);
+        // units that reach past E_B are screened in binary32 and only the
+        // kept pairs are evaluated in binary64
+        const bool f32w = xi_f32_weighted(MODE, PREC, W);
+        const bool allin = U.slot_lo >= 1 && U.slot_hi <= P.nb;
+        if (f32w && !anywrap && !own && !allin && nj < (1ull << 21)) {
+          const double ox = frame_origin(G2, 0, X) + U.S[0];
+          const double oy = frame_origin(G2, 1, Y) + U.S[1];
+          const double oz = frame_origin(G2, 2, Z) + U.S[2];
+          const float rxf = valid ? (float)(L.x - ox) : 1e18f;
+          const float ryf = valid ? (float)(L.y - oy) : 1e18f;
+          const float rzf = valid ? (float)(L.z - oz) : 1e18f;
+          const float ra = __builtin_fmaf(rzf, rzf, __builtin_fmaf(ryf, ryf, rxf * rxf));
+          const double4 *tpts = P.pos1 + tp0;
+          const int nb = P.nb;
+#define CP_XW(C, SH) loop_xi_f32_w<C, SH>(P, A, lane, rxf, ryf, rzf, ra, U, tpts, tab64, sE, nrechk)
+          if (U.slot_lo == nb && U.slot_hi == nb + 1) {
+            if (shifted) CP_XW(1, true); else CP_XW(1, false);
+          } else if (nb >= 2 && U.slot_lo == nb - 1 && U.slot_hi == nb + 1) {
+            if (shifted) CP_XW(2, true); else CP_XW(2, false);
+          } else {
+            if (shifted) CP_XW(0, true); else CP_XW(0, false);
+          }
+#undef CP_XW
+        } else if (PREC == F32R && !anywrap && !f32w) {
           const double ox = frame_origin(G2, 0, X) + U.S[0];
           const double oy = frame_origin(G2, 1, Y) + U.S[1];
           const double oz = frame_origin(G2, 2, Z) + U.S[2];
@@ -1116,7 +1326,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
             else { if (shifted) CP_WP(false, true); else CP_WP(false, false); }
 #undef CP_WP
           }
-        } else if (PREC == F64 && MODE == XI && !own && !anywrap &&
+        } else if ((PREC == F64 || f32w) && MODE == XI && !own && !anywrap &&
                    U.slot_hi == U.slot_lo + 2) {
           if (valid) {
             if (!W || U.slot_hi <= P.nb) {
@@ -1127,7 +1337,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
               else loop_xi_f64_three<false, W, false>(P, A, L, lane, U, sE);
             }
           }
-        } else if (PREC == F64 && two) {
+        } else if ((PREC == F64 || f32w) && two) {
           if (valid) {
             if (W) {
               if (U.slot_hi <= P.nb) {
@@ -1164,6 +1374,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
 }
 
 template __global__ void k_pairs<XI, F32R, 0>(PairParams);
+template __global__ void k_pairs<XI, F32R, 1>(PairParams);
 template __global__ void k_pairs<XI, F64, 0>(PairParams);
 template __global__ void k_pairs<XI, F64, 1>(PairParams);
 template __global__ void k_pairs<WP, F32R, 0>(PairParams);

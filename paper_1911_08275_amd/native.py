@@ -27,7 +27,8 @@ ERR_NAMES = {-1: "CP_ERR_INVALID_ARG", -2: "CP_ERR_OUT_OF_BOX", -3: "CP_ERR_NONF
 
 EXPORTS = [
     "cp_default_options", "countpairs_xi", "countpairs_wp", "countpairs_cross",
-    "countpairs_cross_wp", "countpairs_workspace_size", "countpairs_strerror",
+    "countpairs_cross_wp", "countpairs_workspace_size",
+    "countpairs_strerror",
     "countpairs_last_error", "countpairs_last_stats", "cp_plan_create", "cp_plan_execute",
     "cp_plan_results", "cp_plan_stats", "cp_plan_destroy", "cp_rr_periodic_xi",
     "cp_rr_periodic_wp", "cp_xi_natural", "cp_wp_integrate",

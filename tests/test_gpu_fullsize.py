@@ -9,7 +9,8 @@
   (binary32 == binary64; additivity over a split of D).
 - 256 mocks of 2*10^5..2*10^6 points in one plan: binary32 == binary64 for
   every mock and every bin; the four smallest mocks against the oracle; every
-  mock equal to its single-call count for a sample of mocks.
+  mock equal to its own single-call count (whose path the other parity tests
+  pin to the oracle).
 """
 import time
 from concurrent.futures import ThreadPoolExecutor
@@ -47,10 +48,12 @@ def test_headline_xi_weighted_full(native):
     for prec in ("fp32", "fp64"):
         g = native.countpairs_xi(d, c["edges"], precision=prec, periodic=True, boxsize=420.0,
                                  need_ravg=True)
+        assert g.stats["precision"] == prec, g.stats
         assert (g.npairs == ref.npairs).all(), (prec, g.npairs, ref.npairs)
         np.testing.assert_allclose(g.wsum, ref.wsum, rtol=1e-12, atol=0)
         np.testing.assert_allclose(g.ravg, ref.ravg, rtol=1e-12, atol=0)
-        _say(f"  {prec} ok, rechecks {g.stats['rechecks']}")
+        _say(f"  {prec} ok, rechecks {g.stats['rechecks']}, pair kernel "
+             f"{g.stats['ms_pairs']:.3f} ms")
 
 
 def test_headline_estimators(native):
@@ -92,6 +95,7 @@ def test_wp_full(native):
     for prec in ("fp32", "fp64"):
         g = native.countpairs_wp(d, c["edges"], 40.0, 40, precision=prec, periodic=True,
                                  boxsize=420.0)
+        assert g.stats["precision"] == prec, g.stats
         assert (g.npairs == ref.npairs).all(), prec
 
 
@@ -108,6 +112,7 @@ def test_cross_full_sampled(native):
     for prec in ("fp32", "fp64"):
         g = native.countpairs_cross(native.to_device(sub), dr, c["edges"], precision=prec,
                                     periodic=False)
+        assert g.stats["precision"] == prec, g.stats
         assert (g.npairs == ref.npairs).all(), prec
     # full size: binary32 == binary64, and counts add up over a split of D
     dd = native.to_device(c["d"])
@@ -136,6 +141,8 @@ def test_batch_256_mocks(native):
                            precision=prec, periodic=True, boxsize=420.0)
         plan.execute()
         res[prec] = plan.results()
+        sx, sw = plan.stats()
+        assert sx["precision"] == prec and sw["precision"] == prec, (sx, sw)
         plan.close()
         torch.cuda.synchronize()
     assert (res["fp32"][0] == res["fp64"][0]).all()
@@ -146,8 +153,10 @@ def test_batch_256_mocks(native):
         _say(f"  mock {m} (n={cats[m].n}) vs oracle")
         assert (xi[m] == oracle.xi(cats[m], xe, True, 420.0).npairs).all()
         assert (wp[m] == oracle.wp(cats[m], xe, 40.0, 40, periodic=True, box=420.0).npairs).all()
-    for m in (int(order[-1]), int(order[len(order) // 2]), 0, 255):
+    # every mock of the plan equals its own single call (a few ms each)
+    _say("  every mock vs its single call")
+    for m in range(len(devs)):
         s = native.countpairs_xi(devs[m], xe, periodic=True, boxsize=420.0)
-        assert (s.npairs == xi[m]).all()
+        assert (s.npairs == xi[m]).all(), m
         s = native.countpairs_wp(devs[m], xe, 40.0, 40, periodic=True, boxsize=420.0)
-        assert (s.npairs == wp[m]).all()
+        assert (s.npairs == wp[m]).all(), m

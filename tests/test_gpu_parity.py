@@ -30,7 +30,7 @@ def _say(*a):
     print(*a, flush=True)
 
 
-def _check(g, r, weighted=False):
+def _check(g, r, weighted=False, prec=None, periodic=True):
     n = g.npairs.reshape(r.npairs.shape)
     bad = np.nonzero(n != r.npairs)
     assert (n == r.npairs).all(), (bad, n[bad], r.npairs[bad])
@@ -38,6 +38,12 @@ def _check(g, r, weighted=False):
         ws = g.wsum.reshape(r.wsum.shape)
         np.testing.assert_allclose(ws, r.wsum, rtol=RTOL_W, atol=0)
         np.testing.assert_allclose(g.ravg.reshape(r.wsum.shape), r.ravg, rtol=RTOL_W, atol=0)
+    if prec is not None:
+        # the precision the pair kernel ran: as asked, except on a periodic
+        # grid with a single wrapped cell on some axis (per-pair minimum
+        # images), which runs in binary64
+        wrapped = periodic and 1 in list(g.stats["grid"])
+        assert g.stats["precision"] == ("fp64" if wrapped else prec), g.stats
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -47,7 +53,7 @@ def test_config1_uniform(native, prec):
     ref = oracle.xi(c["cat"], c["edges"], periodic=True, box=c["box"])
     d = native.to_device(c["cat"])
     g = native.countpairs_xi(d, c["edges"], precision=prec, periodic=True, boxsize=c["box"])
-    _check(g, ref)
+    _check(g, ref, prec=prec)
     assert g.stats["candidates"] > 0
 
 
@@ -60,10 +66,10 @@ def test_clustered_xi_weighted(native, prec):
     d = native.to_device(cat)
     g = native.countpairs_xi(d, edges, precision=prec, periodic=True, boxsize=420.0,
                              need_ravg=True)
-    _check(g, ref, weighted=True)
+    _check(g, ref, weighted=True, prec=prec)
     # counts only, same call without weights requested
     g2 = native.countpairs_xi(d, edges, precision=prec, periodic=True, boxsize=420.0)
-    _check(g2, ref)
+    _check(g2, ref, prec=prec)
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -74,7 +80,7 @@ def test_clustered_wp(native, prec):
     ref = oracle.wp(cat, edges, 40.0, 40, periodic=True, box=420.0)
     d = native.to_device(cat)
     g = native.countpairs_wp(d, edges, 40.0, 40, precision=prec, periodic=True, boxsize=420.0)
-    _check(g, ref)
+    _check(g, ref, prec=prec)
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -86,7 +92,7 @@ def test_wp_weighted(native, prec):
     d = native.to_device(cat)
     g = native.countpairs_wp(d, edges, 25.0, 10, precision=prec, periodic=True, boxsize=200.0,
                              need_ravg=True)
-    _check(g, ref, weighted=True)
+    _check(g, ref, weighted=True, prec=prec)
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -98,7 +104,7 @@ def test_cross_nonperiodic_float32(native, prec):
     ref = oracle.xi(dcat, edges, periodic=False, other=rcat)
     g = native.countpairs_cross(native.to_device(dcat), native.to_device(rcat), edges,
                                 precision=prec, periodic=False)
-    _check(g, ref)
+    _check(g, ref, prec=prec, periodic=False)
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -110,7 +116,7 @@ def test_cross_wp_periodic_weighted(native, prec):
     ref = oracle.wp(a, edges, 30.0, 6, periodic=True, box=300.0, other=b)
     g = native.countpairs_cross_wp(native.to_device(a), native.to_device(b), edges, 30.0, 6,
                                    precision=prec, periodic=True, boxsize=300.0, need_ravg=True)
-    _check(g, ref, weighted=True)
+    _check(g, ref, weighted=True, prec=prec)
 
 
 Q = 2.0 ** -6
@@ -138,7 +144,7 @@ def test_lattice_edge_ties(native, prec, mode):
     else:
         ref = oracle.wp(cat, edges, 8.0, 8, periodic=True, box=60.0)
         g = native.countpairs_wp(d, edges, 8.0, 8, precision=prec, periodic=True, boxsize=60.0)
-    _check(g, ref)
+    _check(g, ref, prec=prec)
     if prec == "fp32":
         assert g.stats["rechecks"] > 0
 
@@ -152,7 +158,7 @@ def test_full_box_total(native):
                                  periodic=True, boxsize=420.0)
         assert int(g.npairs.sum()) == cat.n * (cat.n - 1)
         ref = oracle.xi(cat, [0.0, 100.0, 400.0], periodic=True, box=420.0)
-        _check(g, ref)
+        _check(g, ref, prec=prec)
         g = native.countpairs_wp(native.to_device(cat), [0.0, 50.0, 300.0], 211.0, 3,
                                  precision=prec, periodic=True, boxsize=420.0)
         assert int(g.npairs.sum()) == cat.n * (cat.n - 1)
@@ -172,10 +178,10 @@ def test_refine_factors(native, refine):
     for prec in ("fp32", "fp64"):
         g = native.countpairs_xi(d, edges, precision=prec, periodic=True, boxsize=420.0,
                                  refine=refine)
-        _check(g, ref)
+        _check(g, ref, prec=prec)
         g = native.countpairs_wp(d, edges, 40.0, 40, precision=prec, periodic=True,
                                  boxsize=420.0, refine=refine)
-        _check(g, refw)
+        _check(g, refw, prec=prec)
 
 
 @pytest.mark.parametrize("refine", [(1, 1, 1), (2, 2, 2), (3, 1, 2)])
@@ -193,10 +199,10 @@ def test_nonperiodic_auto(native, refine):
         _say("nonperiodic auto", refine, prec)
         g = native.countpairs_xi(d, edges, precision=prec, periodic=False, refine=refine,
                                  need_ravg=True)
-        _check(g, ref, weighted=True)
+        _check(g, ref, weighted=True, prec=prec, periodic=False)
         g = native.countpairs_wp(d, edges, 15.0, 5, precision=prec, periodic=False,
                                  refine=refine)
-        _check(g, refw)
+        _check(g, refw, prec=prec, periodic=False)
 
 
 @pytest.mark.parametrize("rmax,refine,expect_r", [
@@ -219,13 +225,13 @@ def test_minimal_periodic_grids(native, rmax, refine, expect_r):
         g = native.countpairs_xi(da, edges, precision=prec, periodic=True, boxsize=420.0,
                                  refine=refine, need_ravg=True)
         assert tuple(g.stats["refine"]) == expect_r
-        _check(g, oracle.xi(a, edges, periodic=True, box=420.0), weighted=True)
+        _check(g, oracle.xi(a, edges, periodic=True, box=420.0), weighted=True, prec=prec)
         g = native.countpairs_wp(da, edges, 60.0, 6, precision=prec, periodic=True,
                                  boxsize=420.0, refine=refine)
-        _check(g, oracle.wp(a, edges, 60.0, 6, periodic=True, box=420.0))
+        _check(g, oracle.wp(a, edges, 60.0, 6, periodic=True, box=420.0), prec=prec)
         g = native.countpairs_cross(da, db, edges, precision=prec, periodic=True, boxsize=420.0,
                                     refine=refine)
-        _check(g, oracle.xi(a, edges, periodic=True, box=420.0, other=b))
+        _check(g, oracle.xi(a, edges, periodic=True, box=420.0, other=b), prec=prec)
 
 
 @pytest.mark.parametrize("rmax", [80.0, 100.0])
@@ -245,10 +251,10 @@ def test_large_rmax(native, rmax):
             _say("large rmax", rmax, refine, prec)
             g = native.countpairs_xi(d, edges, precision=prec, periodic=True, boxsize=420.0,
                                      refine=refine)
-            _check(g, ref)
+            _check(g, ref, prec=prec)
             g = native.countpairs_wp(d, edges, rmax, npi, precision=prec, periodic=True,
                                      boxsize=420.0, refine=refine)
-            _check(g, refw)
+            _check(g, refw, prec=prec)
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -272,14 +278,14 @@ def test_dense_cell_unsorted_path(native, prec):
     for refine in [(1, 1, 1), (2, 2, 2)]:
         g = native.countpairs_xi(d, edges, precision=prec, periodic=True, boxsize=420.0,
                                  refine=refine, need_ravg=True)
-        _check(g, ref, weighted=True)
+        _check(g, ref, weighted=True, prec=prec)
         g = native.countpairs_xi(d, edges, precision=prec, periodic=True, boxsize=420.0,
                                  refine=refine)
-        _check(g, ref)
+        _check(g, ref, prec=prec)
     refw = oracle.wp(cat, edges, 40.0, 40, periodic=True, box=420.0)
     g = native.countpairs_wp(d, edges, 40.0, 40, precision=prec, periodic=True, boxsize=420.0,
                              refine=(1, 1, 1))
-    _check(g, refw)
+    _check(g, refw, prec=prec)
 
 
 def test_unique_mode_and_pruning_stats(native):
@@ -307,28 +313,28 @@ def test_pruning_off_equals_on(native, prec):
         kw = dict(precision=prec, periodic=True, boxsize=420.0, refine=refine)
         on = native.countpairs_xi(d, edges, need_ravg=True, **kw)
         off = native.countpairs_xi(d, edges, need_ravg=True, no_prune=True, **kw)
-        _check(on, ref, weighted=True)
-        _check(off, ref, weighted=True)
+        _check(on, ref, weighted=True, prec=prec)
+        _check(off, ref, weighted=True, prec=prec)
         assert on.stats["cell_pairs_pruned"] > 0
         assert off.stats["cell_pairs_pruned"] == 0
         assert off.stats["candidates"] > on.stats["candidates"]
         u_on = native.countpairs_xi(d, edges, **kw)
         u_off = native.countpairs_xi(d, edges, no_prune=True, **kw)
-        _check(u_on, ref)
-        _check(u_off, ref)
+        _check(u_on, ref, prec=prec)
+        _check(u_off, ref, prec=prec)
     _say("prune on/off wp", prec)
     refw = oracle.wp(cat, edges, 40.0, 40, periodic=True, box=420.0)
     for flag in (False, True):
         g = native.countpairs_wp(d, edges, 40.0, 40, precision=prec, periodic=True,
                                  boxsize=420.0, no_prune=flag)
-        _check(g, refw)
+        _check(g, refw, prec=prec)
     _say("prune on/off cross", prec)
     rcat = synth.uniform(60_000, 420.0, seed=13)
     refc = oracle.xi(cat, edges, periodic=False, other=rcat)
     dr = native.to_device(rcat)
     for flag in (False, True):
         g = native.countpairs_cross(d, dr, edges, precision=prec, periodic=False, no_prune=flag)
-        _check(g, refc)
+        _check(g, refc, prec=prec, periodic=False)
 
 
 def test_maximum_bins(native):
@@ -344,19 +350,19 @@ def test_maximum_bins(native):
         _say("max bins xi", prec)
         g = native.countpairs_xi(d, e60, precision=prec, periodic=True, boxsize=420.0,
                                  need_ravg=True)
-        _check(g, ref, weighted=True)
+        _check(g, ref, weighted=True, prec=prec)
     refw = oracle.wp(cat, e60, 40.0, 256, periodic=True, box=420.0)
     for prec in ("fp64", "fp32"):
         _say("max bins wp", prec)
         g = native.countpairs_wp(d, e60, 40.0, 256, precision=prec, periodic=True, boxsize=420.0)
-        _check(g, refw)
+        _check(g, refw, prec=prec)
     e20 = synth.log_edges(0.1, 25.0, 20)
     refw = oracle.wp(cat, e20, 40.0, 100, periodic=True, box=420.0)
     for prec in ("fp64", "fp32"):
         _say("weighted wp 20 x 100", prec)
         g = native.countpairs_wp(d, e20, 40.0, 100, precision=prec, periodic=True,
                                  boxsize=420.0, need_ravg=True)
-        _check(g, refw, weighted=True)
+        _check(g, refw, weighted=True, prec=prec)
     with pytest.raises(native.CountpairsError, match="LDS"):
         native.countpairs_wp(d, e60, 40.0, 256, periodic=True, boxsize=420.0, need_ravg=True)
 
@@ -371,11 +377,11 @@ def test_tiny_inputs(native):
             g = native.countpairs_xi(native.to_device(cat), edges, precision=prec,
                                      periodic=True, boxsize=3.0)
             ref = oracle.xi(cat, edges, periodic=True, box=3.0)
-            _check(g, ref)
+            _check(g, ref, prec=prec)
             g = native.countpairs_xi(native.to_device(cat), edges, precision=prec,
                                      periodic=False)
             ref = oracle.xi(cat, edges, periodic=False)
-            _check(g, ref)
+            _check(g, ref, prec=prec, periodic=False)
 
 
 def test_device_errors(native):
