@@ -152,6 +152,28 @@ int countpairs_wp(const cp_points *d, const double *rp_edges, int nedges,
                   uint64_t *npairs, double *wsum, double *rpavg);
 
 /*
+ * countpairs_xi without any allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, results and errors as
+ * countpairs_xi, except:
+ *   - its device scratch is a static array of the library (64 MiB per device,
+ *     held by every device the library runs on until the process ends), not
+ *     the thread's cached buffers; a call that needs more (roughly more than
+ *     500 000 points, depending on the grid) fails with CP_ERR_NOMEM and a
+ *     message giving both sizes;
+ *   - o->workspace must be NULL (CP_ERR_INVALID_ARG otherwise);
+ *   - it creates no HIP events, so the ms_* fields of countpairs_last_stats
+ *     are 0; it calls no hipMalloc/hipFree and no other allocating routine;
+ *   - every call on one device shares that device's scratch: calls that
+ *     overlap on one device (two host threads, or two streams) race and give
+ *     undefined results.  The call still synchronises o->stream before it
+ *     returns, so calls made one after the other are safe.
+ */
+int countpairs_xi_noalloc(const cp_points *d, const double *edges, int nedges,
+                          const cp_options *o, uint64_t *npairs, double *wsum,
+                          double *ravg);
+
+/*
  * xi(r) cross-count: every ordered pair (i in d1, j in d2) (Section 1.1: the
  * DR and RR terms of survey geometries; Section 2.1: no symmetry for cross
  * correlations).  count_mode is ignored.  Pair weight w1_i * w2_j.

@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -471,6 +472,11 @@ struct Call {
   double pimax;
   int npi;
   const cp_options *o;
+  // the entry point without allocation: its device scratch (the library's
+  // static array) in place of the workspace or the thread's arena; such a
+  // call creates no events and copies results straight into the outputs
+  void *scratch = nullptr;
+  size_t scratch_bytes = 0;
 };
 
 static int check_points(const cp_points *p, const char *name) {
@@ -734,6 +740,7 @@ static int run(const Call &c, uint64_t *npairs, double *wsum, double *ravg) {
   const bool weighted = o.need_ravg != 0;
   const double rmax = c.edges[nb];
 
+  const bool noalloc = c.scratch != nullptr;
   hipEvent_t ev[4] = {};
   struct EvGuard {
     hipEvent_t *e;
@@ -742,8 +749,10 @@ static int run(const Call &c, uint64_t *npairs, double *wsum, double *ravg) {
         if (e[i]) (void)hipEventDestroy(e[i]);
     }
   } evg{ev};
-  for (auto &e : ev) HIPCHK(hipEventCreate(&e));
-  HIPCHK(hipEventRecord(ev[0], st));
+  if (!noalloc) {
+    for (auto &e : ev) HIPCHK(hipEventCreate(&e));
+    HIPCHK(hipEventRecord(ev[0], st));
+  }
 
   PointsDev pd[2];
   auto fillpd = [](const cp_points &p, PointsDev &d) {
@@ -768,7 +777,10 @@ static int run(const Call &c, uint64_t *npairs, double *wsum, double *ravg) {
     const int nblk = 256;
     const size_t pre = sizeof(double) * (6 * nblk + 6) + 64;
     double *d_part = nullptr;
-    if (o.workspace) {
+    if (noalloc) {
+      if (c.scratch_bytes < pre) return fail(CP_ERR_NOMEM, "static scratch too small");
+      d_part = (double *)c.scratch;
+    } else if (o.workspace) {
       if (o.workspace_bytes < pre) return fail(CP_ERR_NOMEM, "workspace too small");
       d_part = (double *)o.workspace;
     } else {
@@ -855,7 +867,14 @@ static int run(const Call &c, uint64_t *npairs, double *wsum, double *ravg) {
     layout(dry, S1, S2, d_sm, d_t32, d_t64, d_E, d_hist, d_hw, d_hwr, d_stats, d_err);
     const size_t need = dry.off + 256;
     void *base;
-    if (o.workspace) {
+    if (noalloc) {
+      if (need > c.scratch_bytes)
+        return fail(CP_ERR_NOMEM, "this call needs " + std::to_string(need) +
+                                      " bytes of device scratch; the static scratch of "
+                                      "countpairs_xi_noalloc holds " +
+                                      std::to_string(c.scratch_bytes));
+      base = c.scratch;
+    } else if (o.workspace) {
       if (o.workspace_bytes < need)
         return fail(CP_ERR_NOMEM, "workspace too small: need " + std::to_string(need) + " bytes");
       base = o.workspace;
@@ -934,7 +953,7 @@ static int run(const Call &c, uint64_t *npairs, double *wsum, double *ravg) {
                       d_sm->maxspan, d_err, false);
     if (rc) return rc;
   }
-  HIPCHK(hipEventRecord(ev[1], st));
+  if (!noalloc) HIPCHK(hipEventRecord(ev[1], st));
 
   // ---- pairs
   PairParams P;
@@ -987,14 +1006,25 @@ static int run(const Call &c, uint64_t *npairs, double *wsum, double *ravg) {
   const int nwaves = pick_waves(LY, &lds);
   if (!nwaves) return fail(CP_ERR_INVALID_ARG, "too many bins for the LDS budget");
   if ((rc = launch_pairs(st, c.mode, prec, weighted, P, lds, nwaves))) return rc;
-  HIPCHK(hipEventRecord(ev[2], st));
+  if (!noalloc) HIPCHK(hipEventRecord(ev[2], st));
 
   // ---- results
   unsigned long long hst[kStatWords];
   int eflag = 0;
   std::vector<unsigned long long> h;
   std::vector<double> hwv, hwrv;
-  {
+  if (noalloc) {
+    // straight into the caller's outputs (raw counts and sums, finished
+    // in place below), statistics and error flag on the stack
+    HIPCHK(hipMemcpyAsync(npairs, d_hist, 8 * (size_t)nout, hipMemcpyDeviceToHost, st));
+    if (weighted) {
+      HIPCHK(hipMemcpyAsync(wsum, d_hw, 8 * (size_t)nout, hipMemcpyDeviceToHost, st));
+      HIPCHK(hipMemcpyAsync(ravg, d_hwr, 8 * (size_t)nout, hipMemcpyDeviceToHost, st));
+    }
+    HIPCHK(hipMemcpyAsync(hst, d_stats, sizeof(hst), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(&eflag, d_err, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+  } else {
     // histogram, weight sums, statistics and the error flag are carved
     // consecutively, so one download brings them all
     h.resize(nout);
@@ -1028,7 +1058,7 @@ static int run(const Call &c, uint64_t *npairs, double *wsum, double *ravg) {
     }
   }
   if (rc) {
-    // failed calls leave zero outputs
+    // failed calls leave zero outputs (the raw sums were copied into them)
     memset(npairs, 0, sizeof(uint64_t) * nout);
     if (o.need_ravg) {
       memset(wsum, 0, sizeof(double) * nout);
@@ -1039,9 +1069,10 @@ static int run(const Call &c, uint64_t *npairs, double *wsum, double *ravg) {
 
   const double mult = (autoc && o.count_mode == CP_ORDERED) ? 2.0 : 1.0;
   for (int k = 0; k < nout; k++) {
-    const unsigned long long hk = h[k];
-    const double w = hwv[k];
-    const double wr = hwrv[k];
+    // noalloc: npairs, wsum and ravg hold the raw count and sums
+    const unsigned long long hk = noalloc ? npairs[k] : h[k];
+    const double w = noalloc ? (weighted ? wsum[k] : 0.0) : hwv[k];
+    const double wr = noalloc ? (weighted ? ravg[k] : 0.0) : hwrv[k];
     npairs[k] = (uint64_t)hk * (uint64_t)mult;
     if (weighted) {
       wsum[k] = w * mult;
@@ -1058,11 +1089,44 @@ static int run(const Call &c, uint64_t *npairs, double *wsum, double *ravg) {
     g_stats.grid[a] = g.n[a];
     g_stats.refine[a] = g.r[a];
   }
-  (void)hipEventElapsedTime(&g_stats.ms_grid, ev[0], ev[1]);
-  (void)hipEventElapsedTime(&g_stats.ms_pairs, ev[1], ev[2]);
-  (void)hipEventElapsedTime(&g_stats.ms_total, ev[0], ev[3]);
+  if (!noalloc) {
+    (void)hipEventElapsedTime(&g_stats.ms_grid, ev[0], ev[1]);
+    (void)hipEventElapsedTime(&g_stats.ms_pairs, ev[1], ev[2]);
+    (void)hipEventElapsedTime(&g_stats.ms_total, ev[0], ev[3]);
+  }
   g_stats.precision = prec == F32R ? CP_PREC_FP32_RECHECK : CP_PREC_FP64;
   g_stats_valid = true;
+  return CP_OK;
+}
+
+// ------------------------------------------------- static device scratch
+//
+// Device scratch of countpairs_xi_noalloc: a file-scope array that every
+// device the library runs on holds from module load until the process ends.
+// Host code never uses the array's name as an address: its device address
+// comes from hipGetSymbolAddress, once per device with that device current
+// (on the device's first such call), and is kept per device.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxDevices];
+
+static int static_scratch(void **out) {
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(CP_ERR_DEVICE, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(CP_ERR_DEVICE, std::string("hipGetSymbolAddress(scratch): ") +
+                                     hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
   return CP_OK;
 }
 
@@ -1097,6 +1161,22 @@ int countpairs_wp(const cp_points *d, const double *rp_edges, int nedges, double
   try {
     Call c{WP, false, d, nullptr, rp_edges, nedges, pimax, npibins, o};
     return run(c, npairs, wsum, rpavg);
+  } catch (...) {
+    return fail(CP_ERR_INTERNAL, "unexpected exception");
+  }
+}
+
+int countpairs_xi_noalloc(const cp_points *d, const double *edges, int nedges,
+                          const cp_options *o, uint64_t *npairs, double *wsum, double *ravg) {
+  try {
+    if (o && o->workspace)
+      return fail(CP_ERR_INVALID_ARG,
+                  "countpairs_xi_noalloc takes no workspace: it uses the library's static scratch");
+    void *sp = nullptr;
+    int rc = static_scratch(&sp);
+    if (rc) return rc;
+    Call c{XI, false, d, nullptr, edges, nedges, 0.0, 1, o, sp, kScratchBytes};
+    return run(c, npairs, wsum, ravg);
   } catch (...) {
     return fail(CP_ERR_INTERNAL, "unexpected exception");
   }

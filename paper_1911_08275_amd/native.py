@@ -27,7 +27,7 @@ ERR_NAMES = {-1: "CP_ERR_INVALID_ARG", -2: "CP_ERR_OUT_OF_BOX", -3: "CP_ERR_NONF
 
 EXPORTS = [
     "cp_default_options", "countpairs_xi", "countpairs_wp", "countpairs_cross",
-    "countpairs_cross_wp", "countpairs_workspace_size",
+    "countpairs_cross_wp", "countpairs_xi_noalloc", "countpairs_workspace_size",
     "countpairs_strerror",
     "countpairs_last_error", "countpairs_last_stats", "cp_plan_create", "cp_plan_execute",
     "cp_plan_results", "cp_plan_stats", "cp_plan_destroy", "cp_rr_periodic_xi",
@@ -89,10 +89,12 @@ def lib() -> ctypes.CDLL:
         L.cp_default_options.restype = None
         L.countpairs_xi.argtypes = [pp, D, ctypes.c_int, po, U, D, D]
         L.countpairs_wp.argtypes = [pp, D, ctypes.c_int, ctypes.c_double, ctypes.c_int, po, U, D, D]
+        L.countpairs_xi_noalloc.argtypes = [pp, D, ctypes.c_int, po, U, D, D]
         L.countpairs_cross.argtypes = [pp, pp, D, ctypes.c_int, po, U, D, D]
         L.countpairs_cross_wp.argtypes = [pp, pp, D, ctypes.c_int, ctypes.c_double, ctypes.c_int,
                                           po, U, D, D]
-        for f in ("countpairs_xi", "countpairs_wp", "countpairs_cross", "countpairs_cross_wp"):
+        for f in ("countpairs_xi", "countpairs_wp", "countpairs_cross", "countpairs_cross_wp",
+                  "countpairs_xi_noalloc"):
             getattr(L, f).restype = ctypes.c_int
         L.countpairs_workspace_size.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_int64, D,
                                                 ctypes.c_int, ctypes.c_double, ctypes.c_int, po]
@@ -267,6 +269,18 @@ def countpairs_xi(d: DevicePoints, edges, **opt) -> Counts:
     _check(lib().countpairs_xi(ctypes.byref(pts), _dp(e), e.size, ctypes.byref(o), _up(n),
                                _dp(ws) if ws is not None else None,
                                _dp(ra) if ra is not None else None))
+    return Counts(n, ws, ra, last_stats())
+
+
+def countpairs_xi_noalloc(d: DevicePoints, edges, **opt) -> Counts:
+    """countpairs_xi on the library's static device scratch (no allocation)."""
+    e = np.ascontiguousarray(edges, dtype=np.float64)
+    o = options(**opt)
+    n, ws, ra = _outputs(e.size - 1, o.need_ravg)
+    pts = d.struct()
+    _check(lib().countpairs_xi_noalloc(ctypes.byref(pts), _dp(e), e.size, ctypes.byref(o),
+                                       _up(n), _dp(ws) if ws is not None else None,
+                                       _dp(ra) if ra is not None else None))
     return Counts(n, ws, ra, last_stats())
 
 
