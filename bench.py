@@ -32,13 +32,23 @@ sys.path.insert(0, ROOT)
 
 from paper_1911_08275_amd import synth  # noqa: E402
 
-# VALU lane-operation peak of the MI355X: 256 CUs x 64 lanes per clock x 2.4 GHz
-# (the unpacked, unfused vector rate: half of the 78.6 TFLOP/s that counts an
-# FMA as two operations)
+# VALU issue peak of the MI355X: 256 CUs x 64 lanes per clock x 2.4 GHz =
+# 39.3e12 lane-operations per second (one unpacked, unfused vector operation
+# per lane and clock; an FMA counts once).  Published FLOP peaks (an FMA
+# counts twice): binary64 vector 78.6, binary32 vector 157.3 (packed) TFLOP/s.
 PEAK_LANE_OPS = 256 * 64 * 2.4e9
-OPS_PER_CANDIDATE = 9        # 3 sub, 3 mul, 2 add, 1 compare
-OPS_PER_INRANGE = 2          # bin locate + count
-OPS_PER_INRANGE_WEIGHTED = 7  # bin locate + count, sqrt, w_i*w_j, times r, two sums
+PEAK_FLOPS = {"f64": 78.6e12, "f32": 157.3e12}
+# Algorithmic work per pair (lane-operations, flops):
+#   xi binary64 candidate: 3 sub, 3 mul, 2 add, 1 compare      -> 9 ops, 8 flops
+#   xi binary32 candidate: 3 FMA, 1 add, 1 compare (Gram form,
+#     unpacked: packed binary32 arithmetic is not used)          -> 5 ops, 7 flops
+#   wp binary64 candidate: 3 sub, 2 mul, 1 add, 2 compares       -> 8 ops, 6 flops
+#   wp binary32 candidate: 2 FMA, 1 add, 1 sub, 2 compares       -> 6 ops, 6 flops
+#   in-range pair: bin locate + count (wp: two bins)             -> 2 (3) ops
+#   weighted in-range pair: bin + count, sqrt, w_i w_j, x r, 2 sums -> 7 ops, 5 flops
+WORK = {("xi", "f64"): (9, 8), ("xi", "f32"): (5, 7), ("wp", "f64"): (8, 6), ("wp", "f32"): (6, 6)}
+INRANGE_OPS = {"xi": 2, "wp": 3}
+WEIGHTED_OPS, WEIGHTED_FLOPS = 7, 5
 
 
 def log(*a):
@@ -93,14 +103,85 @@ def measured_traffic(refine):
     return None
 
 
-def roofline(cand, inrange_unique, ms_pairs, weighted):
-    ops = OPS_PER_CANDIDATE * cand + (OPS_PER_INRANGE_WEIGHTED if weighted else OPS_PER_INRANGE) \
-        * inrange_unique
-    ach = ops / (ms_pairs * 1e-3) / 1e12
+def roofline(stat, prec, cand, inrange, ms_pairs, weighted=False):
+    """Algorithmic work of one pair-kernel launch over its HIP-event time.
+    cand: candidate pairs evaluated (cp_stats.candidates); inrange: pairs
+    counted by the kernel (unique pairs for an auto-count)."""
+    cop, cfl = WORK[(stat, prec)]
+    ops = cop * cand + (WEIGHTED_OPS if weighted else INRANGE_OPS[stat]) * inrange
+    flops = cfl * cand + (WEIGHTED_FLOPS if weighted else 0) * inrange
+    t = ms_pairs * 1e-3
+    ach = ops / t / 1e12
     peak = PEAK_LANE_OPS / 1e12
     return {"bound": "alu", "achieved": round(ach, 3), "peak": round(peak, 3),
-            "unit": "TFLOP/s", "frac": round(ach / peak, 4), "traffic": None,
-            "kernel": "k_pairs (pair kernel)", "ops_per_launch": int(ops)}
+            "unit": "T lane-ops/s", "frac": round(ach / peak, 4), "traffic": None,
+            "kernel": "k_pairs (pair kernel)", "ops_per_launch": int(ops),
+            "flops_per_launch": int(flops), "flop_frac": round(flops / t / PEAK_FLOPS[prec], 4),
+            "flop_peak_tflops": PEAK_FLOPS[prec] / 1e12, "ms_kernel": round(ms_pairs, 4)}
+
+
+def smi_query():
+    """Shader and memory clock (MHz) and power cap (W) of GPU 0 from
+    rocm-smi, or None."""
+    import re
+    import subprocess
+    try:
+        out = subprocess.run(["rocm-smi", "--showclocks", "--showmaxpower", "--json"],
+                             capture_output=True, text=True, timeout=30).stdout
+        d = json.loads(out[out.index("{"):])
+    except Exception:
+        return None
+    card = next((v for k, v in d.items() if k.lower().startswith("card")), None)
+    if not isinstance(card, dict):
+        return None
+    res = {}
+    for k, v in card.items():
+        kl, vs = k.lower(), str(v).lower()
+        m = re.search(r"(\d+(?:\.\d+)?)\s*mhz", vs)
+        if "sclk" in kl and m:
+            res["sclk_mhz"] = float(m.group(1))
+        elif "mclk" in kl and m:
+            res["mclk_mhz"] = float(m.group(1))
+        elif "power" in kl and "max" in kl:
+            n = re.search(r"\d+(?:\.\d+)?", vs)
+            if n:
+                res["power_cap_w"] = float(n.group(0))
+    return res or None
+
+
+def clocks_under_load(fn, seconds):
+    """Runs fn() back to back for about `seconds` while a thread samples
+    rocm-smi; returns the shader clocks seen (MHz) and the power cap."""
+    import threading
+    import torch
+    samples, caps = [], []
+    stop = threading.Event()
+
+    def poll():
+        while not stop.is_set():
+            q = smi_query()
+            if q and "sclk_mhz" in q:
+                samples.append(q["sclk_mhz"])
+                if "power_cap_w" in q:
+                    caps.append(q["power_cap_w"])
+            if q is None:
+                return
+    th = threading.Thread(target=poll, daemon=True)
+    th.start()
+    t0 = time.time()
+    while time.time() - t0 < seconds:
+        fn()
+    torch.cuda.synchronize()
+    stop.set()
+    th.join(timeout=40)
+    return samples, (caps[0] if caps else None)
+
+
+def rocm_version():
+    try:
+        return open("/opt/rocm/.info/version").read().strip()
+    except OSError:
+        return None
 
 
 def _median_call(fn, steps):
@@ -285,26 +366,50 @@ def main():
                                         need_ravg=weighted, **rk)
         return f
 
-    # Weighted xi runs in binary64 whatever the precision flag (the weighted
-    # mean needs every counted pair's binary64 separation), so the headline is
-    # timed once; the binary32 filter is compared on the unweighted counts.
+    def mean_ms(stats, key="ms_pairs"):
+        return float(np.mean([x.stats[key] for x in stats]))
+
+    # Headline: weighted xi.  Every counted pair needs its binary64 separation;
+    # the library runs the binary64 kernel in either precision mode (measured
+    # faster on gfx950) unless CP_XI_WEIGHTED_BINARY32=1 selects the binary32
+    # screen, which is timed beside it.
     dtw, sw = time_steps(step("fp64"), args.steps, args.warmup)
-    log(f"c2 weighted: {dtw * 1e3:.3f} ms/step", sw[-1].stats)
+    log(f"c2 weighted (binary64): {dtw * 1e3:.3f} ms/step", sw[-1].stats)
+    os.environ["CP_XI_WEIGHTED_BINARY32"] = "1"
+    try:
+        dtws, sws = time_steps(step("fp32"), max(3, args.steps // 2), 1)
+    finally:
+        del os.environ["CP_XI_WEIGHTED_BINARY32"]
+    log(f"c2 weighted (binary32 screen): {dtws * 1e3:.3f} ms/step", sws[-1].stats)
     dt32, s32 = time_steps(step("fp32", False), max(3, args.steps // 2), 1)
     log(f"c2 unweighted fp32+recheck: {dt32 * 1e3:.3f} ms/step", s32[-1].stats)
     dt64, s64 = time_steps(step("fp64", False), max(3, args.steps // 2), 1)
     log(f"c2 unweighted fp64: {dt64 * 1e3:.3f} ms/step", s64[-1].stats)
-    gw, g32, g64 = sw[-1], s32[-1], s64[-1]
-    exact = bool((g32.npairs == g64.npairs).all() and (gw.npairs == g64.npairs).all())
+    gw, gws, g32, g64 = sw[-1], sws[-1], s32[-1], s64[-1]
+    exact = bool((g32.npairs == g64.npairs).all() and (gw.npairs == g64.npairs).all()
+                 and (gws.npairs == g64.npairs).all())
     pairs = int(gw.npairs.sum())                  # ordered in-range pairs
-    ms_w = float(np.mean([s.stats["ms_pairs"] for s in sw]))
-    ms_pairs32 = float(np.mean([s.stats["ms_pairs"] for s in s32]))
-    ms_pairs64 = float(np.mean([s.stats["ms_pairs"] for s in s64]))
+    uniq = pairs // 2                             # pairs the kernel counts
+    ms_w = mean_ms(sw)
     st = gw.stats
-    roof = roofline(st["candidates"], pairs // 2, ms_w, True)
+    roof = roofline("xi", "f64", st["candidates"], uniq, ms_w, weighted=True)
     roof["traffic"] = measured_traffic(st["refine"])
-    roof32 = roofline(g32.stats["candidates"], pairs // 2, ms_pairs32, False)
-    roof64 = roofline(g64.stats["candidates"], pairs // 2, ms_pairs64, False)
+    roof_ws = roofline("xi", "f32", gws.stats["candidates"], uniq, mean_ms(sws), weighted=True)
+    roof32 = roofline("xi", "f32", g32.stats["candidates"], uniq, mean_ms(s32))
+    roof64 = roofline("xi", "f64", g64.stats["candidates"], uniq, mean_ms(s64))
+
+    # shader clock under load (rocm-smi sampled while the headline runs back
+    # to back, outside the timed steps), power cap, ROCm version
+    idle = smi_query()
+    sclk, cap = clocks_under_load(step("fp64"), 3.0)
+    machine = {"rocm": rocm_version(),
+               "sclk_mhz_under_load": {"min": min(sclk), "median": float(np.median(sclk)),
+                                       "max": max(sclk), "samples": len(sclk)} if sclk else None,
+               "sclk_mhz_idle": (idle or {}).get("sclk_mhz"),
+               "mclk_mhz_idle": (idle or {}).get("mclk_mhz"),
+               "power_cap_w": cap if cap is not None else (idle or {}).get("power_cap_w"),
+               "peak_assumes_sclk_mhz": 2400}
+    log("machine:", machine)
 
     out = {
         "metric": "pair evaluations/sec and mocks/sec, FP32+recheck vs FP64, counts bit-exact",
@@ -321,25 +426,35 @@ def main():
         "data": "synthetic",
         "config": {"workload": "xi(r) auto-count, 1e6 Neyman-Scott points (2e4 parents, "
                                "Poisson(50) children, sigma 1.5), periodic L=420, 14 log bins "
-                               "0.1-25, weights U(0.5,1.5) with weighted mean r (binary64 "
-                               "separations for every pair in either precision mode)",
+                               "0.1-25, weights U(0.5,1.5) with weighted mean r; binary64 kernel "
+                               "(what either precision mode runs for weighted xi)",
                    "n": c2["cat"].n, "nbins": 14, "rmax": 25.0, "box": 420.0,
                    "grid": st["grid"], "refine": st["refine"]},
         "pairs_per_step": pairs,
         "candidates_per_step": st["candidates"],
         "candidate_rate": st["candidates"] / dtw,
+        "candidates_per_inrange_pair": st["candidates"] / max(1, uniq),
         "ms_pairs_kernel": ms_w,
-        "ms_grid": float(np.mean([s.stats["ms_grid"] for s in sw])),
+        "ms_grid": mean_ms(sw, "ms_grid"),
+        "weighted_binary32_screen": {
+            "value": pairs / dtws, "ms_per_step": dtws * 1e3, "ms_pairs_kernel": mean_ms(sws),
+            "precision_ran": gws.stats["precision"],
+            "recheck_fraction": gws.stats["rechecks"] / max(1, uniq),
+            "roofline_frac": roof_ws["frac"], "flop_frac": roof_ws["flop_frac"],
+            "over_binary64": dtw / dtws},
         "unweighted": {
             "fp32": {"value": pairs / dt32, "ms_per_step": dt32 * 1e3,
-                     "ms_pairs_kernel": ms_pairs32, "refine": g32.stats["refine"],
-                     "recheck_fraction": g32.stats["rechecks"] / max(1, pairs // 2),
-                     "roofline_frac": roof32["frac"]},
+                     "ms_pairs_kernel": mean_ms(s32), "refine": g32.stats["refine"],
+                     "candidates": g32.stats["candidates"],
+                     "recheck_fraction": g32.stats["rechecks"] / max(1, uniq),
+                     "roofline_frac": roof32["frac"], "flop_frac": roof32["flop_frac"]},
             "fp64": {"value": pairs / dt64, "ms_per_step": dt64 * 1e3,
-                     "ms_pairs_kernel": ms_pairs64, "refine": g64.stats["refine"],
-                     "roofline_frac": roof64["frac"]},
+                     "ms_pairs_kernel": mean_ms(s64), "refine": g64.stats["refine"],
+                     "candidates": g64.stats["candidates"],
+                     "roofline_frac": roof64["frac"], "flop_frac": roof64["flop_frac"]},
             "fp32_over_fp64": dt64 / dt32},
         "counts_equal_fp32_fp64_weighted": exact,
+        "machine": machine,
         "roofline": roof,
     }
 
@@ -356,11 +471,18 @@ def main():
             res[prec] = (dt, ss[-1])
             log(f"c3 wp {prec}: {dt * 1e3:.3f} ms/step", ss[-1].stats)
         p3 = int(res["fp32"][1].npairs.sum())
+
+        def leg(stat, prec, pairs_, counted, dt, g):
+            r = roofline(stat, "f32" if prec == "fp32" else "f64", g.stats["candidates"],
+                         counted, g.stats["ms_pairs"])
+            return {"value": pairs_ / dt, "ms": dt * 1e3, "ms_pairs_kernel": g.stats["ms_pairs"],
+                    "candidates": g.stats["candidates"], "refine": g.stats["refine"],
+                    "precision_ran": g.stats["precision"],
+                    "recheck_fraction": g.stats["rechecks"] / max(1, counted),
+                    "roofline_frac": r["frac"], "flop_frac": r["flop_frac"]}
         extras["wp_c3"] = {"pairs_per_step": p3,
-                           "fp32": {"value": p3 / res["fp32"][0], "ms": res["fp32"][0] * 1e3,
-                                    "ms_pairs_kernel": res["fp32"][1].stats["ms_pairs"]},
-                           "fp64": {"value": p3 / res["fp64"][0], "ms": res["fp64"][0] * 1e3,
-                                    "ms_pairs_kernel": res["fp64"][1].stats["ms_pairs"]},
+                           "fp32": leg("wp", "fp32", p3, p3 // 2, *res["fp32"]),
+                           "fp64": leg("wp", "fp64", p3, p3 // 2, *res["fp64"]),
                            "counts_equal": bool((res["fp32"][1].npairs ==
                                                  res["fp64"][1].npairs).all())}
         del d3
@@ -376,8 +498,8 @@ def main():
             log(f"c4 cross {prec}: {dt * 1e3:.3f} ms/step", ss[-1].stats)
         p4 = int(res["fp32"][1].npairs.sum())
         extras["cross_c4"] = {"pairs_per_step": p4,
-                              "fp32": {"value": p4 / res["fp32"][0], "ms": res["fp32"][0] * 1e3},
-                              "fp64": {"value": p4 / res["fp64"][0], "ms": res["fp64"][0] * 1e3},
+                              "fp32": leg("xi", "fp32", p4, p4, *res["fp32"]),
+                              "fp64": leg("xi", "fp64", p4, p4, *res["fp64"]),
                               "counts_equal": bool((res["fp32"][1].npairs ==
                                                     res["fp64"][1].npairs).all())}
         del dd, dr
@@ -422,6 +544,15 @@ def main():
                 "graph_ms": bres["fp32"][3]["ms_total"],
                 "xi_candidates": bres["fp32"][3]["candidates"],
                 "wp_candidates": bres["fp32"][4]["candidates"]}
+            # roofline of the whole evaluation (cell builds included, so a
+            # lower bound for the pair kernels): binary32 work of both
+            # statistics over the wall time of one graph replay
+            px, pw = int(bres["fp32"][1].sum()) // 2, int(bres["fp32"][2].sum()) // 2
+            ops = (WORK[("xi", "f32")][0] * bres["fp32"][3]["candidates"] + INRANGE_OPS["xi"] * px +
+                   WORK[("wp", "f32")][0] * bres["fp32"][4]["candidates"] + INRANGE_OPS["wp"] * pw)
+            extras["batch_c5"]["roofline_frac_incl_build"] = round(ops / dt / PEAK_LANE_OPS, 4)
+            extras["batch_c5"]["recheck_fraction"] = (
+                (bres["fp32"][3]["rechecks"] + bres["fp32"][4]["rechecks"]) / max(1, px + pw))
             del devs
             torch.cuda.empty_cache()
     if extras:

@@ -25,7 +25,8 @@
  *   - counts are exact.  CP_PREC_FP32_RECHECK evaluates distances in binary32
  *     with a derived error bound and re-evaluates in binary64 every pair whose
  *     binary32 value could lie on the other side of an edge, so its counts are
- *     identical to CP_PREC_FP64's.
+ *     identical to CP_PREC_FP64's (cp_stats.precision tells which precision
+ *     a call ran; see there for the cases that run binary64).
  *   - weighted outputs: wsum_k = sum of w_i * w_j, ravg_k = sum of
  *     w_i * w_j * sep / wsum_k (sep = r for xi, rp for wp; 0 for empty bins).
  *     They are binary64 sums in an unspecified order (relative error far
@@ -112,11 +113,17 @@ typedef struct {
   float ms_grid;             /* device time of the cell build (ms) */
   float ms_pairs;            /* device time of the pair kernel (ms) */
   float ms_total;            /* device time of the whole call (ms) */
-  int precision;             /* CP_PREC_* the pair kernel actually ran: a grid
-                                with a single wrapped cell on some axis (box
-                                under three cells of reach) takes per-pair
-                                minimum images and runs in binary64 whatever
-                                was asked for */
+  int precision;             /* CP_PREC_* the pair kernel actually ran.  Binary64
+                                runs whatever was asked for (a) on a grid with a
+                                single wrapped cell on some axis (box under
+                                three cells of reach: per-pair minimum images)
+                                and (b) for weighted xi (need_ravg), where every
+                                counted pair needs its binary64 separation and
+                                the binary64 kernel is faster on gfx950; the
+                                environment variable CP_XI_WEIGHTED_BINARY32=1
+                                selects the binary32 screen for (b) instead
+                                (candidates screened in binary32, the surviving
+                                pairs evaluated in binary64: same counts) */
 } cp_stats;
 
 /* Fill *o with defaults: FP32 recheck, non-periodic, refine 0 (library

@@ -168,10 +168,8 @@ __host__ __device__ constexpr bool xi_f32_weighted(int mode, int prec, int weigh
   return mode == XI && prec == F32R && weighted;
 }
 // List entries per wave: fewer than 64 are left over after a drain, and a
-// group of four records adds at most 4 x 64; then one dummy entry per lane,
-// written by lanes that keep nothing (the append has no branch).
+// group of four records adds at most 4 x 64.
 constexpr int kListCap = 64 + 4 * 64;
-constexpr int kListWords = kListCap + 64;
 
 __host__ __device__ inline LdsLayout lds_layout(int mode, int prec, int weighted, int n32, int n64,
                                                int nb, int npi) {
@@ -191,7 +189,7 @@ __host__ __device__ inline LdsLayout lds_layout(int mode, int prec, int weighted
   // weight sums are shared by the wave (one row of slots), not lane-private
   L.wave_w = weighted ? (mode == XI ? (size_t)NS * kWStripe : words) * 8 : 0;
   L.wave_list = L.wave_hist + 2 * L.wave_w;
-  L.wave_bytes = L.wave_list + (xi_f32_weighted(mode, prec, weighted) ? (size_t)kListWords * 4 : 0);
+  L.wave_bytes = L.wave_list + (xi_f32_weighted(mode, prec, weighted) ? (size_t)kListCap * 4 : 0);
   return L;
 }
 

@@ -678,8 +678,7 @@ __device__ inline void wait_lgkm() { __builtin_amdgcn_s_waitcnt(0xC07F); }
 // SH: the unit has a periodic shift (added to each binary64 difference).
 // A list entry holds byte offsets: (record << 11) | (tile lane << 5), so the
 // unit may have at most 2^21 records.  Records go four at a time; the list
-// holds at most 63 + 4 x 64 entries, and lanes that keep nothing write a
-// dummy entry of their own, so the append needs no branch.  The look-ahead
+// holds at most 63 + 4 x 64 entries.  The look-ahead
 // may read up to 7 records past the unit (the stream arrays are padded past
 // their end); the last group masks the records past the unit.
 // exec = all lanes: list entries go to lanes regardless of the tile's size.
@@ -779,10 +778,12 @@ __device__ inline void loop_xi_f32_w(const PairParams &P, WaveArea A, int lane, 
     const float d = gram3(rx, ry, rz, ra, qx, qy, qz, qw);
     const bool keep = d < AB && (!check || jr < nrec);
     const unsigned long long m = __builtin_amdgcn_ballot_w64(keep);
-    const uint32_t at = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
-                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-    list[keep ? (uint32_t)tail + at : (uint32_t)(kListCap + lane)] = ((uint32_t)jr << 11) | lane32;
-    tail += (int)__popcll(m);
+    if (m) {
+      const uint32_t at = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+      if (keep) list[tail + at] = ((uint32_t)jr << 11) | lane32;
+      tail += (int)__popcll(m);
+    }
   };
   sfloat *p = (sfloat *)(U.strm + U.jb);
   float a[16];

@@ -1,7 +1,8 @@
 """GPU parity at the full workload sizes (the benchmark's configurations).
 
-- xi, 10^6 clustered points, weighted (the headline workload): both
-  precisions against the oracle over the whole catalogue.
+- xi, 10^6 clustered points, weighted (the headline workload): binary64 (what
+  both precision modes run by default) and the binary32 screen against the
+  oracle over the whole catalogue.
 - wp 2-D histogram, same generator: both precisions against the oracle.
 - float32 cross count D(10^6) x R(10^7), non-periodic: the oracle on a random
   sample of D against all of R (the GPU counts the same sample against the
@@ -38,17 +39,20 @@ def native():
     return native
 
 
-def test_headline_xi_weighted_full(native):
+def test_headline_xi_weighted_full(native, monkeypatch):
     c = synth.config2()
     _say("headline xi weighted: oracle")
     t = time.time()
     ref = oracle.xi(c["cat"], c["edges"], periodic=True, box=420.0)
     _say(f"  oracle {time.time() - t:.1f}s")
     d = native.to_device(c["cat"])
-    for prec in ("fp32", "fp64"):
+    # binary64 (both modes by default), then the binary32 screen switched on
+    for prec, screen in (("fp32", False), ("fp64", False), ("fp32", True)):
+        if screen:
+            monkeypatch.setenv("CP_XI_WEIGHTED_BINARY32", "1")
         g = native.countpairs_xi(d, c["edges"], precision=prec, periodic=True, boxsize=420.0,
                                  need_ravg=True)
-        assert g.stats["precision"] == prec, g.stats
+        assert g.stats["precision"] == ("fp32" if screen else "fp64"), g.stats
         assert (g.npairs == ref.npairs).all(), (prec, g.npairs, ref.npairs)
         np.testing.assert_allclose(g.wsum, ref.wsum, rtol=1e-12, atol=0)
         np.testing.assert_allclose(g.ravg, ref.ravg, rtol=1e-12, atol=0)

@@ -5,6 +5,8 @@ separations within 1e-12 relative.  Sizes here let the oracle finish in
 seconds while still spanning many tiles, ragged tiles and shifted periodic
 cells; the full-size workloads are in test_gpu_fullsize.py.
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -41,9 +43,11 @@ def _check(g, r, weighted=False, prec=None, periodic=True):
     if prec is not None:
         # the precision the pair kernel ran: as asked, except on a periodic
         # grid with a single wrapped cell on some axis (per-pair minimum
-        # images), which runs in binary64
+        # images) and for weighted xi (unless the binary32 screen is asked
+        # for), which run in binary64
         wrapped = periodic and 1 in list(g.stats["grid"])
-        assert g.stats["precision"] == ("fp64" if wrapped else prec), g.stats
+        w_xi = weighted and r.npairs.ndim == 1 and os.environ.get("CP_XI_WEIGHTED_BINARY32") != "1"
+        assert g.stats["precision"] == ("fp64" if (wrapped or w_xi) else prec), g.stats
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -70,6 +74,37 @@ def test_clustered_xi_weighted(native, prec):
     # counts only, same call without weights requested
     g2 = native.countpairs_xi(d, edges, precision=prec, periodic=True, boxsize=420.0)
     _check(g2, ref, prec=prec)
+
+
+def test_xi_weighted_binary32_screen(native, monkeypatch):
+    """Weighted xi with the binary32 screen switched on
+    (CP_XI_WEIGHTED_BINARY32=1): candidates screened in binary32, the pairs
+    that survive evaluated in binary64 from the wave's list; counts equal the
+    oracle, sums within 1e-12, on a clustered periodic catalogue at several
+    refine factors and with pruning off, a non-periodic one and a cross
+    count."""
+    monkeypatch.setenv("CP_XI_WEIGHTED_BINARY32", "1")
+    cat = synth.clustered(60_000, 1200, 1.5, 420.0, seed=2, weights=True)
+    edges = synth.log_edges(0.1, 25.0, 14)
+    ref = oracle.xi(cat, edges, periodic=True, box=420.0)
+    d = native.to_device(cat)
+    for refine in ((2, 2, 2), (1, 1, 1), (3, 3, 2)):
+        for noprune in (False, True):
+            _say("xi weighted binary32 screen", refine, noprune)
+            g = native.countpairs_xi(d, edges, precision="fp32", periodic=True, boxsize=420.0,
+                                     need_ravg=True, refine=refine, no_prune=noprune)
+            _check(g, ref, weighted=True, prec="fp32")
+    c = synth.clustered(8_000, 200, 2.0, 200.0, seed=51, weights=True)
+    np_cat = synth.Catalog(c.x - 20.0, c.y * 0.75 + 5.0, c.z * 0.5, c.w)
+    e2 = synth.log_edges(0.5, 20.0, 10)
+    g = native.countpairs_xi(native.to_device(np_cat), e2, precision="fp32", periodic=False,
+                             need_ravg=True)
+    _check(g, oracle.xi(np_cat, e2, periodic=False), weighted=True, prec="fp32", periodic=False)
+    b = synth.uniform(40_000, 420.0, seed=22, weights=True)
+    g = native.countpairs_cross(d, native.to_device(b), edges, precision="fp32", periodic=True,
+                                boxsize=420.0, need_ravg=True)
+    _check(g, oracle.xi(cat, edges, periodic=True, box=420.0, other=b), weighted=True,
+           prec="fp32")
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
