@@ -19,6 +19,7 @@ bounded sample of the headline workload.
 from __future__ import annotations
 
 import argparse
+import glob
 import json
 import os
 import sys
@@ -69,8 +70,7 @@ def time_steps(fn, steps, warmup):
     return dt, stats
 
 
-TRAFFIC_FILES = [os.path.join(ROOT, "profiles", f) for f in
-                 ("k_pairs_xi_weighted_1e6_traffic.md", "k_pairs_xi_weighted_1e6_traffic_r222.md")]
+TRAFFIC_FILES = sorted(glob.glob(os.path.join(ROOT, "profiles", "k_pairs_xi_weighted_1e6_traffic*.md")))
 KERNEL_SRC = os.path.join(ROOT, "paper_1911_08275_amd", "csrc", "pair_kernels.hip")
 
 
@@ -325,6 +325,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-batch", action="store_true", help="skip the 256-mock batch")
     ap.add_argument("--refine", type=str, default=None, help="e.g. 2,2,1")
+    ap.add_argument("--no-clock", action="store_true",
+                    help="skip rocm-smi (shader clock under load, power cap): profiled runs")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain device copy of known size (counter calibration)")
     ap.add_argument("--sweep", choices=("refine", "rmax"), default=None,
@@ -400,8 +402,9 @@ def main():
 
     # shader clock under load (rocm-smi sampled while the headline runs back
     # to back, outside the timed steps), power cap, ROCm version
-    idle = smi_query()
-    sclk, cap = clocks_under_load(step("fp64"), 3.0)
+    # (rocm-smi is a script started through /usr/bin/env: profiled runs skip it)
+    idle = None if args.no_clock else smi_query()
+    sclk, cap = ([], None) if args.no_clock else clocks_under_load(step("fp64"), 3.0)
     machine = {"rocm": rocm_version(),
                "sclk_mhz_under_load": {"min": min(sclk), "median": float(np.median(sclk)),
                                        "max": max(sclk), "samples": len(sclk)} if sclk else None,

@@ -1,5 +1,6 @@
 """The benchmark's command-line contract and its committed counter summaries
 (no GPU needed)."""
+import glob
 import os
 import re
 import subprocess
@@ -17,8 +18,15 @@ def test_more_than_one_gpu_exits_with_message():
     assert "one GPU" in r.stderr
 
 
-@pytest.mark.parametrize("name", ["k_pairs_xi_weighted_1e6_traffic.md",
-                                  "k_pairs_xi_weighted_1e6_traffic_r222.md"])
+TRAFFIC = sorted(os.path.basename(p) for p in glob.glob(
+    os.path.join(ROOT, "profiles", "k_pairs_xi_weighted_1e6_traffic*.md")))
+
+
+def test_traffic_summary_exists():
+    assert TRAFFIC
+
+
+@pytest.mark.parametrize("name", TRAFFIC)
 def test_traffic_summaries_parse(name):
     """Each traffic summary carries the fields bench.py reads: the kernel
     source hash, the refine factors and the per-launch byte counts."""
