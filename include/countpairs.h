@@ -87,8 +87,22 @@ typedef struct {
   int precision;          /* CP_PREC_FP64 or CP_PREC_FP32_RECHECK */
   int periodic;           /* 1: cube [0, boxsize)^3, minimum-image separations */
   double boxsize;         /* side of the periodic cube (ignored otherwise) */
-  int refine[3];          /* cells per R_max (pi_max along z for wp) per axis;
-                             0 = library default (Section 3.1 bin_refine_factors) */
+  int refine[3];          /* cells per R_max (pi_max along z for wp) per axis
+                             (Section 3.1 bin_refine_factors).  All three 0: the
+                             library chooses the refine factors, the queue
+                             items' work-chunk target and the waves per
+                             workgroup by timing candidates on the call's own
+                             data (best of two whole calls each, coordinate
+                             descent), and caches the choice per workload
+                             signature (statistic, precision, weights, periodic,
+                             log2 of the point counts and of the expected
+                             neighbours per point, pi_max / R_max) in memory and
+                             in a JSON file: $CP_AUTOTUNE_CACHE, else
+                             $HOME/.cache/paper_1911_08275_amd/autotune.json.
+                             The first call of a signature runs about 24 timed
+                             calls.  CP_AUTOTUNE=0 in the environment switches
+                             tuning off (refine 2,2,2).  Counts do not depend
+                             on the choice. */
   int need_ravg;          /* 1: fill wsum and ravg */
   int count_mode;         /* CP_ORDERED (default) or CP_UNIQUE, auto-counts only */
   void *stream;           /* hipStream_t; NULL = null stream */
@@ -124,10 +138,18 @@ typedef struct {
                                 selects the binary32 screen for (b) instead
                                 (candidates screened in binary32, the surviving
                                 pairs evaluated in binary64: same counts) */
+  int tuned;                 /* launch settings: 0 given by the caller (refine
+                                set), 1 tuned during this call, 2 taken from
+                                the tuning cache, 3 library defaults (tuning
+                                switched off, or a cache miss in
+                                countpairs_xi_noalloc) */
+  int chunk_pct;             /* work-chunk target of the queue items, percent
+                                of the library's estimate */
+  int waves;                 /* waves per pair-kernel workgroup */
 } cp_stats;
 
-/* Fill *o with defaults: FP32 recheck, non-periodic, refine 0 (library
- * default), no ravg, ordered counts, null stream, library scratch. */
+/* Fill *o with defaults: FP32 recheck, non-periodic, refine 0 (tuned by the
+ * library), no ravg, ordered counts, null stream, library scratch. */
 void cp_default_options(cp_options *o);
 
 /*
@@ -218,6 +240,9 @@ int countpairs_last_stats(cp_stats *out);
  *                    execute, so the caller may refill them in place);
  *                    xi_edges / wp_edges may be NULL to skip that statistic;
  *                    o: precision, refine, periodic (must be 1) and boxsize.
+ *                    refine 0: the settings are tuned (and cached) by timing
+ *                    single calls of the requested statistics on the median
+ *                    catalogue.
  *   cp_plan_execute  enqueue one evaluation on stream (asynchronous).
  *   cp_plan_results  synchronise the stream of the last execute and copy counts:
  *                    xi_npairs nmocks*(xi_nedges-1), wp_npairs

@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcountpairs.so")
-SOURCES = ["api.hip", "grid_kernels.hip", "pair_kernels.hip", "estimators.cpp"]
+SOURCES = ["api.hip", "grid_kernels.hip", "pair_kernels.hip", "estimators.cpp", "tune_cache.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

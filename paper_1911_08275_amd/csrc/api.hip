@@ -296,7 +296,7 @@ static Geometry choose_geometry(int mode, bool periodic, double box, const doubl
 // finer split for the end of the queue (fitted to timings from R_max = 5 to
 // 100).
 static void split_columns(const Geometry &g, bool autoc, double reach, double reach_z,
-                          double npts2, double cost, PairParams &P) {
+                          double npts2, double cost, int chunk_pct, PairParams &P) {
   const int rx = g.r[0], ry = g.r[1], ncy = 2 * ry + 1;
   const int ncols = autoc ? 1 + ry + rx * ncy : (2 * rx + 1) * ncy;
   Fixed<double, (2 * 8 + 1) * (2 * 8 + 1) + 1> cum;   // columns + 1 at refine 8 per axis
@@ -333,6 +333,7 @@ static void split_columns(const Geometry &g, bool autoc, double reach, double re
     const double c = npts2 / vol * g.cs[0] * g.cs[1] * (2.0 * reach_z + g.cs[2]) * cost;
     per = std::min(12.0, std::max(2.2, 4.5 * std::sqrt(137.0 / std::max(c, 1e-9))));
   }
+  per *= chunk_pct * 0.01;   // the autotuner's scale of the target
   int m = (int)std::lround(tot / per);
   m = std::max(1, std::min(m, std::min(kMaxChunks, ncols)));
   P.nsplit = m;
@@ -477,6 +478,9 @@ struct Call {
   // call creates no events and copies results straight into the outputs
   void *scratch = nullptr;
   size_t scratch_bytes = 0;
+  // launch settings that refine = 0 leaves to the library (0: defaults)
+  int chunk_pct = 0;
+  int waves = 0;
 };
 
 static int check_points(const cp_points *p, const char *name) {
@@ -575,8 +579,8 @@ static int num_cus() {
 // Waves per pair-kernel workgroup: four, or fewer when the per-wave
 // histograms (w_p with many bins, weighted) would not fit the 160 KB of LDS;
 // 0 when not even one wave's fits.
-static int pick_waves(const LdsLayout &LY, size_t *lds) {
-  for (int nw = 4; nw >= 1; nw--) {
+static int pick_waves(const LdsLayout &LY, size_t *lds, int most = 4) {
+  for (int nw = std::min(4, std::max(1, most)); nw >= 1; nw--) {
     const size_t l = LY.common + (size_t)nw * LY.wave_bytes;
     if (l + kStaticLds <= 160 * 1024) {
       *lds = l;
@@ -707,6 +711,109 @@ static int map_err_flags(int flags) {
   return CP_OK;
 }
 
+// ------------------------------------------------------------- autotuning
+//
+// refine = 0 on every axis leaves the launch settings to the library
+// (Section 3.1: the run time varies by up to 50 % with the refine factors,
+// whose automatic choice the paper names as future work).  Candidates are
+// timed on the call's own data -- device time of whole calls, best of two --
+// by coordinate descent: the refine factors first, then the work-chunk
+// target of the queue items, then the waves per workgroup; the winner is
+// cached per workload signature (tune_cache.cpp).  CP_AUTOTUNE=0 switches
+// tuning off (library defaults).
+
+static const int kRefineCands[][3] = {{2, 2, 2}, {2, 2, 1}, {2, 2, 3}, {3, 3, 2},
+                                      {3, 3, 3}, {1, 1, 1}, {4, 4, 3}};
+static const int kChunkCands[] = {70, 140};
+static const int kWaveCands[] = {2};
+
+static bool autotune_on() {
+  const char *e = getenv("CP_AUTOTUNE");
+  return !(e && e[0] == '0');
+}
+
+// statistic, precision, weights, periodic, log2 of the point counts and of
+// the expected neighbours per point within reach, pi_max / R_max for wp
+static std::string tune_key(const Call &c, double volume) {
+  const cp_options &o = *c.o;
+  const int64_t n1 = c.d1 ? c.d1->n : 0;
+  const int64_t n2 = c.cross && c.d2 ? c.d2->n : n1;
+  const double R = c.edges[c.nedges - 1];
+  const double reach = c.mode == XI ? 4.0 / 3.0 * M_PI * R * R * R : M_PI * R * R * 2.0 * c.pimax;
+  const double neigh = std::max(1.0, (double)n2) * reach / std::max(volume, 1e-300);
+  auto l2 = [](double v) { return (int)std::lround(std::log2(std::max(v, 1e-3))); };
+  std::string k = std::string(c.mode == XI ? "xi" : "wp") + (c.cross ? "-cross" : "") +
+                  (o.precision == CP_PREC_FP64 ? "/fp64" : "/fp32") + (o.need_ravg ? "/w" : "/u") +
+                  (o.periodic ? "/p" : "/n") + "/n" + std::to_string(l2((double)std::max<int64_t>(n1, 1)));
+  if (c.cross) k += "/m" + std::to_string(l2((double)std::max<int64_t>(n2, 1)));
+  k += "/k" + std::to_string(l2(neigh));
+  if (c.mode == WP) k += "/z" + std::to_string((int)std::lround(2.0 * std::log2(c.pimax / R)));
+  return k;
+}
+
+static int run(const Call &c, uint64_t *npairs, double *wsum, double *ravg);
+
+// Times the candidates on every call of `calls` (the objective is their sum)
+// and stores the best settings under key.
+static int tune(const std::vector<Call> &calls, const std::string &key, TuneChoice &best) {
+  std::vector<cp_options> opts;
+  for (const Call &c : calls) opts.push_back(*c.o);
+  std::vector<uint64_t> n;
+  std::vector<double> w, r;
+  auto time_of = [&](const int ref[3], int chunk, int waves, double &ms) -> int {
+    ms = 0.0;
+    for (size_t i = 0; i < calls.size(); i++) {
+      Call c = calls[i];
+      cp_options &o = opts[i];
+      for (int a = 0; a < 3; a++) o.refine[a] = ref[a];
+      c.o = &o;
+      c.chunk_pct = chunk;
+      c.waves = waves;
+      const size_t nout = (size_t)(c.nedges - 1) * (c.mode == WP ? c.npi : 1);
+      n.assign(nout, 0);
+      w.assign(nout, 0.0);
+      r.assign(nout, 0.0);
+      double t = INFINITY;
+      for (int rep = 0; rep < 2; rep++) {
+        const int rc = run(c, n.data(), o.need_ravg ? w.data() : nullptr,
+                           o.need_ravg ? r.data() : nullptr);
+        if (rc) return rc;
+        t = std::min(t, (double)g_stats.ms_total);
+      }
+      ms += t;
+    }
+    return CP_OK;
+  };
+  best = TuneChoice();
+  best.ms = INFINITY;
+  // a candidate that does not fit a caller's workspace is skipped
+  auto consider = [&](const int ref[3], int chunk, int waves) -> int {
+    double ms;
+    const int rc = time_of(ref, chunk, waves, ms);
+    if (rc == CP_ERR_NOMEM) return CP_OK;
+    if (rc) return rc;
+    if (ms < best.ms) {
+      for (int a = 0; a < 3; a++) best.refine[a] = ref[a];
+      best.chunk_pct = chunk;
+      best.waves = waves;
+      best.ms = ms;
+    }
+    return CP_OK;
+  };
+  int rc;
+  for (const auto &ref : kRefineCands)
+    if ((rc = consider(ref, 100, 4))) return rc;
+  if (!std::isfinite(best.ms)) return fail(CP_ERR_NOMEM, "no tuning candidate fits the workspace");
+  const int bref[3] = {best.refine[0], best.refine[1], best.refine[2]};
+  for (int ch : kChunkCands)
+    if ((rc = consider(bref, ch, 4))) return rc;
+  const int bch = best.chunk_pct;
+  for (int wv : kWaveCands)
+    if ((rc = consider(bref, bch, wv))) return rc;
+  tune_store(key, best);
+  return CP_OK;
+}
+
 // ------------------------------------------------------------- single call
 
 static int run(const Call &c, uint64_t *npairs, double *wsum, double *ravg) {
@@ -821,8 +928,32 @@ static int run(const Call &c, uint64_t *npairs, double *wsum, double *ravg) {
     }
   }
   const int64_t ntot = p1.n + (autoc ? 0 : p2.n);
+  // launch settings: the caller's refine, or tuned / cached (refine 0)
+  int refine_eff[3] = {o.refine[0], o.refine[1], o.refine[2]};
+  int chunk_pct = c.chunk_pct > 0 ? c.chunk_pct : 100;
+  int waves_most = c.waves > 0 ? c.waves : 4;
+  int tuned = 0;
+  if (!refine_eff[0] && !refine_eff[1] && !refine_eff[2]) {
+    TuneChoice tc;
+    tuned = 3;
+    if (autotune_on()) {
+      const double vol = o.periodic ? o.boxsize * o.boxsize * o.boxsize : ext[0] * ext[1] * ext[2];
+      const std::string key = tune_key(c, vol);
+      if (tune_lookup(key, tc)) {
+        tuned = 2;
+      } else if (!noalloc) {
+        if ((rc = tune({c}, key, tc))) return rc;
+        tuned = 1;
+        // the call's own timing starts after the tuning runs
+        if (!noalloc) HIPCHK(hipEventRecord(ev[0], st));
+      }
+    }
+    for (int a = 0; a < 3; a++) refine_eff[a] = tc.refine[a];
+    chunk_pct = tc.chunk_pct;
+    waves_most = tc.waves;
+  }
   Geometry g = choose_geometry(c.mode, o.periodic != 0, o.boxsize, lo, ext, rmax, c.pimax,
-                               o.refine, ntot);
+                               refine_eff, ntot);
   int prec = o.precision == CP_PREC_FP32_RECHECK ? F32R : F64;
   if (g.wrap[0] || g.wrap[1] || g.wrap[2]) prec = F64;   // per-pair minimum image: binary64
   // Weighted xi: every counted pair needs its binary64 separation, and on
@@ -971,7 +1102,8 @@ static int run(const Call &c, uint64_t *npairs, double *wsum, double *ravg) {
   P.tiles = S1.tiles;
   P.ntiles = S1.coloff + ncol;
   split_columns(g, autoc, rmax, c.mode == XI ? rmax : c.pimax, (double)p2.n,
-                (prec == F64 ? 2.0 : 1.0) * (weighted ? 2.0 : 1.0) * (c.mode == WP ? 2.5 : 1.0), P);
+                (prec == F64 ? 2.0 : 1.0) * (weighted ? 2.0 : 1.0) * (c.mode == WP ? 2.5 : 1.0),
+                chunk_pct, P);
   P.geom1 = &d_sm->geom[0];
   P.geom2 = &d_sm->geom[1];
   P.pos1 = S1.pos;
@@ -1013,7 +1145,7 @@ static int run(const Call &c, uint64_t *npairs, double *wsum, double *ravg) {
   P.hist_stride = nout;
   const LdsLayout LY = lds_layout(c.mode, prec, weighted, n32, n64, nb, npi);
   size_t lds = 0;
-  const int nwaves = pick_waves(LY, &lds);
+  const int nwaves = pick_waves(LY, &lds, waves_most);
   if (!nwaves) return fail(CP_ERR_INVALID_ARG, "too many bins for the LDS budget");
   if ((rc = launch_pairs(st, c.mode, prec, weighted, P, lds, nwaves))) return rc;
   if (!noalloc) HIPCHK(hipEventRecord(ev[2], st));
@@ -1105,6 +1237,9 @@ static int run(const Call &c, uint64_t *npairs, double *wsum, double *ravg) {
     (void)hipEventElapsedTime(&g_stats.ms_total, ev[0], ev[3]);
   }
   g_stats.precision = prec == F32R ? CP_PREC_FP32_RECHECK : CP_PREC_FP64;
+  g_stats.tuned = tuned;
+  g_stats.chunk_pct = chunk_pct;
+  g_stats.waves = nwaves;
   g_stats_valid = true;
   return CP_OK;
 }
@@ -1298,6 +1433,8 @@ struct Batch {
   int *d_err = nullptr;
   size_t lds = 0;
   int nwaves = 4;
+  int waves_most = 4;      // launch settings from the caller or the tuner
+  int chunk_pct = 100;
   double pimax = 0.0;
   PairParams P{};
 };
@@ -1313,6 +1450,7 @@ struct cp_plan {
   cp::Batch xi, wp;
   int count_mode = CP_ORDERED;
   int noprune = 0;
+  int tuned = 0;                 // as cp_stats.tuned
   void *mem = nullptr;
   hipStream_t cap = nullptr;
   hipStream_t last = nullptr;    // stream of the last execute (results and stats sync it)
@@ -1362,7 +1500,7 @@ static int batch_prepare(cp_plan &pl, Batch &b, int mode, int prec, const double
   b.maxtiles = max_tiles_bound(b.npts_tot, b.ncell_tot, b.ncol_tot);
   const LdsLayout LY = lds_layout(mode, b.prec, 0, (int)b.B.t32.e.size(),
                                        (int)b.B.t64.e.size(), b.nb, b.npi);
-  b.nwaves = pick_waves(LY, &b.lds);
+  b.nwaves = pick_waves(LY, &b.lds, b.waves_most);
   if (!b.nwaves) return fail(CP_ERR_INVALID_ARG, "too many bins for the LDS budget");
   return CP_OK;
 }
@@ -1421,7 +1559,7 @@ static int batch_upload(cp_plan &pl, Batch &b) {
   P.ntiles = b.S.coloff + b.ncol_tot;
   split_columns(b.g, true, std::sqrt(b.B.E[b.nb]), b.mode == XI ? std::sqrt(b.B.E[b.nb]) : b.pimax,
                 (double)b.npts_tot / std::max(1, pl.nmock),
-                (b.prec == F64 ? 2.0 : 1.0) * (b.mode == WP ? 2.5 : 1.0), P);
+                (b.prec == F64 ? 2.0 : 1.0) * (b.mode == WP ? 2.5 : 1.0), b.chunk_pct, P);
   P.geom1 = b.d_geom;
   P.geom2 = b.d_geom;
   P.pos1 = b.S.pos;
@@ -1570,12 +1708,44 @@ int cp_plan_create(const cp_points *mocks, int nmocks, const double *xi_edges, i
       pl->pts.push_back(d);
     }
     const int prec = o->precision == CP_PREC_FP32_RECHECK ? F32R : F64;
-    if (xi_edges && (rc = batch_prepare(*pl, pl->xi, XI, prec, xi_edges, xi_nedges, 0.0, 1, *o))) {
+    // launch settings: the caller's refine, or tuned on the median catalogue
+    // by timing single calls of the requested statistics (cached)
+    cp_options po = *o;
+    po.need_ravg = 0;
+    po.count_mode = CP_ORDERED;
+    TuneChoice tc;
+    if (!po.refine[0] && !po.refine[1] && !po.refine[2]) {
+      pl->tuned = 3;
+      if (autotune_on()) {
+        const int med = pl->order[nmocks / 2];   // order: decreasing size
+        std::vector<Call> calls;
+        if (xi_edges) calls.push_back(Call{XI, false, &mocks[med], nullptr, xi_edges, xi_nedges, 0.0, 1, &po});
+        if (wp_edges)
+          calls.push_back(Call{WP, false, &mocks[med], nullptr, wp_edges, wp_nedges, pimax, npibins, &po});
+        const double vol = po.boxsize * po.boxsize * po.boxsize;
+        const std::string key = "plan:" + tune_key(calls[0], vol) + (calls.size() > 1 ? "+wp" : "");
+        if (tune_lookup(key, tc)) {
+          pl->tuned = 2;
+        } else {
+          if ((rc = tune(calls, key, tc))) {
+            cp_plan_destroy(pl);
+            return rc;
+          }
+          pl->tuned = 1;
+        }
+      }
+      for (int a = 0; a < 3; a++) po.refine[a] = tc.refine[a];
+    }
+    for (Batch *b : {&pl->xi, &pl->wp}) {
+      b->chunk_pct = tc.chunk_pct;
+      b->waves_most = tc.waves;
+    }
+    if (xi_edges && (rc = batch_prepare(*pl, pl->xi, XI, prec, xi_edges, xi_nedges, 0.0, 1, po))) {
       cp_plan_destroy(pl);
       return rc;
     }
     if (wp_edges &&
-        (rc = batch_prepare(*pl, pl->wp, WP, prec, wp_edges, wp_nedges, pimax, npibins, *o))) {
+        (rc = batch_prepare(*pl, pl->wp, WP, prec, wp_edges, wp_nedges, pimax, npibins, po))) {
       cp_plan_destroy(pl);
       return rc;
     }
@@ -1701,6 +1871,9 @@ int cp_plan_stats(cp_plan *pl, cp_stats *xs, cp_stats *ws) {
     o->cell_pairs_pruned = st[3];
     o->tiles = nt;
     o->precision = b.prec == F32R ? CP_PREC_FP32_RECHECK : CP_PREC_FP64;
+    o->tuned = pl->tuned;
+    o->chunk_pct = b.chunk_pct;
+    o->waves = b.nwaves;
     for (int a = 0; a < 3; a++) {
       o->grid[a] = b.g.n[a];
       o->refine[a] = b.g.r[a];

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <string>
+
 namespace cp {
 
 constexpr int kWave = 64;
@@ -34,6 +36,17 @@ constexpr int kWStripe = 8;       // copies of each weight sum per wave (lane & 
 
 // Sets the calling thread's countpairs_last_error text and returns code.
 int report_error(int code, const char *msg);
+
+// Autotuned launch settings of one workload signature (tune_cache.cpp).
+struct TuneChoice {
+  int refine[3] = {2, 2, 2};
+  int chunk_pct = 100;   // scale of the queue items' work-chunk target, percent
+  int waves = 4;         // most waves per pair-kernel workgroup
+  double ms = 0.0;       // device time of the tuned call
+};
+bool tune_lookup(const std::string &key, TuneChoice &out);
+void tune_store(const std::string &key, const TuneChoice &t);
+std::string tune_cache_file();
 
 enum Mode { XI = 0, WP = 1 };
 enum Prec { F64 = 0, F32R = 1 };

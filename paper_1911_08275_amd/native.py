@@ -54,7 +54,8 @@ class cp_stats(ctypes.Structure):
                 ("tiles", ctypes.c_uint64), ("grid", ctypes.c_int * 3),
                 ("refine", ctypes.c_int * 3), ("ms_grid", ctypes.c_float),
                 ("ms_pairs", ctypes.c_float), ("ms_total", ctypes.c_float),
-                ("precision", ctypes.c_int)]
+                ("precision", ctypes.c_int), ("tuned", ctypes.c_int),
+                ("chunk_pct", ctypes.c_int), ("waves", ctypes.c_int)]
 
     def todict(self) -> dict:
         return dict(candidates=int(self.candidates), rechecks=int(self.rechecks),
@@ -63,7 +64,9 @@ class cp_stats(ctypes.Structure):
                     ms_grid=float(self.ms_grid), ms_pairs=float(self.ms_pairs),
                     ms_total=float(self.ms_total),
                     precision={CP_PREC_FP64: "fp64",
-                               CP_PREC_FP32_RECHECK: "fp32"}.get(int(self.precision), "?"))
+                               CP_PREC_FP32_RECHECK: "fp32"}.get(int(self.precision), "?"),
+                    tuned={0: "given", 1: "tuned", 2: "cached", 3: "default"}.get(int(self.tuned), "?"),
+                    chunk_pct=int(self.chunk_pct), waves=int(self.waves))
 
 
 class CountpairsError(RuntimeError):
@@ -186,7 +189,8 @@ def options(precision: str = "fp32", periodic: bool = False, boxsize: float = 0.
     o.precision = {"fp32": CP_PREC_FP32_RECHECK, "fp64": CP_PREC_FP64}[precision]
     o.periodic = 1 if periodic else 0
     o.boxsize = float(boxsize)
-    if refine is not None:
+    if refine is not None and refine != "auto":
+        # None or "auto": refine 0, the library tunes the launch settings
         for a in range(3):
             o.refine[a] = int(refine[a])
     o.need_ravg = 1 if need_ravg else 0
@@ -236,32 +240,7 @@ def _outputs(nout, need):
     return n, ws, ra
 
 
-def _volume(opt, *sets) -> float:
-    if opt.get("periodic"):
-        return float(opt.get("boxsize", 0.0)) ** 3
-    lo = [min(float(getattr(s, a).min()) for s in sets) for a in "xyz"]
-    hi = [max(float(getattr(s, a).max()) for s in sets) for a in "xyz"]
-    return max(1e-300, float(np.prod([h - l for h, l in zip(hi, lo)])))
-
-
-def _auto(kind, fn, sets, edges, pimax, opt):
-    """Resolve refine="auto" through the autotuner, then call fn(**opt)."""
-    if opt.get("refine") != "auto":
-        return fn(**opt)
-    from . import autotune
-    e = np.asarray(edges, dtype=np.float64)
-    sig = autotune.signature(kind, sets[0].n, sets[1].n if len(sets) > 1 else 0,
-                             _volume(opt, *sets), float(e[-1]), float(pimax),
-                             opt.get("precision", "fp32"),
-                             bool(opt.get("need_ravg")), bool(opt.get("periodic")))
-    base = {k: v for k, v in opt.items() if k != "refine"}
-    best = autotune.tune(lambda r: fn(refine=r, **base).stats["ms_total"], sig)
-    return fn(refine=best, **base)
-
-
 def countpairs_xi(d: DevicePoints, edges, **opt) -> Counts:
-    if opt.get("refine") == "auto":
-        return _auto("xi", lambda **o: countpairs_xi(d, edges, **o), [d], edges, 0.0, opt)
     e = np.ascontiguousarray(edges, dtype=np.float64)
     o = options(**opt)
     n, ws, ra = _outputs(e.size - 1, o.need_ravg)
@@ -285,9 +264,6 @@ def countpairs_xi_noalloc(d: DevicePoints, edges, **opt) -> Counts:
 
 
 def countpairs_wp(d: DevicePoints, rp_edges, pimax: float, npibins: int, **opt) -> Counts:
-    if opt.get("refine") == "auto":
-        return _auto("wp", lambda **o: countpairs_wp(d, rp_edges, pimax, npibins, **o), [d],
-                     rp_edges, pimax, opt)
     e = np.ascontiguousarray(rp_edges, dtype=np.float64)
     o = options(**opt)
     n, ws, ra = _outputs((e.size - 1) * npibins, o.need_ravg)
@@ -301,9 +277,6 @@ def countpairs_wp(d: DevicePoints, rp_edges, pimax: float, npibins: int, **opt) 
 
 
 def countpairs_cross(d1: DevicePoints, d2: DevicePoints, edges, **opt) -> Counts:
-    if opt.get("refine") == "auto":
-        return _auto("cross", lambda **o: countpairs_cross(d1, d2, edges, **o), [d1, d2], edges,
-                     0.0, opt)
     e = np.ascontiguousarray(edges, dtype=np.float64)
     o = options(**opt)
     n, ws, ra = _outputs(e.size - 1, o.need_ravg)
@@ -316,10 +289,6 @@ def countpairs_cross(d1: DevicePoints, d2: DevicePoints, edges, **opt) -> Counts
 
 def countpairs_cross_wp(d1: DevicePoints, d2: DevicePoints, rp_edges, pimax: float,
                         npibins: int, **opt) -> Counts:
-    if opt.get("refine") == "auto":
-        return _auto("cross_wp", lambda **o: countpairs_cross_wp(d1, d2, rp_edges, pimax,
-                                                                 npibins, **o),
-                     [d1, d2], rp_edges, pimax, opt)
     e = np.ascontiguousarray(rp_edges, dtype=np.float64)
     o = options(**opt)
     n, ws, ra = _outputs((e.size - 1) * npibins, o.need_ravg)
@@ -339,10 +308,6 @@ class Plan:
     def __init__(self, mocks: Sequence[DevicePoints], xi_edges=None, wp_edges=None,
                  pimax: float = 0.0, npibins: int = 1, **opt):
         self.mocks = list(mocks)
-        if opt.get("refine") == "auto":
-            opt = dict(opt)
-            opt["refine"] = self._tune(xi_edges, wp_edges, pimax, npibins, opt)
-        self.refine = opt.get("refine")
         self._pts = (cp_points * len(self.mocks))(*[m.struct() for m in self.mocks])
         self.xi_edges = None if xi_edges is None else np.ascontiguousarray(xi_edges, np.float64)
         self.wp_edges = None if wp_edges is None else np.ascontiguousarray(wp_edges, np.float64)
@@ -357,29 +322,6 @@ class Plan:
             0 if self.wp_edges is None else self.wp_edges.size,
             float(pimax), self.npibins, ctypes.byref(self._opt), ctypes.byref(h)))
         self.handle = h
-
-    def _tune(self, xi_edges, wp_edges, pimax, npibins, opt):
-        """One refine for both statistics: tuned on the median catalogue by
-        timing single calls of each requested statistic."""
-        from . import autotune
-        med = sorted(self.mocks, key=lambda m: m.n)[len(self.mocks) // 2]
-        base = {k: v for k, v in opt.items() if k != "refine"}
-        e = xi_edges if xi_edges is not None else wp_edges
-        sig = "plan:" + autotune.signature(
-            "xi" if xi_edges is not None else "wp", med.n, 0, _volume(base, med),
-            float(np.asarray(e)[-1]), float(pimax), base.get("precision", "fp32"), False, True)
-        if wp_edges is not None and xi_edges is not None:
-            sig += "+wp"
-
-        def run(r):
-            ms = 0.0
-            if xi_edges is not None:
-                ms += countpairs_xi(med, xi_edges, refine=r, **base).stats["ms_total"]
-            if wp_edges is not None:
-                ms += countpairs_wp(med, wp_edges, pimax, npibins, refine=r,
-                                    **base).stats["ms_total"]
-            return ms
-        return autotune.tune(run, sig)
 
     def execute(self, stream=None):
         if stream is None:

@@ -50,7 +50,7 @@ def test_struct_layouts_match_header(native, tmp_path):
               "cp_options": ["precision", "boxsize", "refine", "stream", "workspace_bytes",
                              "no_prune"],
               "cp_stats": ["candidates", "tiles", "grid", "refine", "ms_grid", "ms_total",
-                           "precision"]}
+                           "precision", "tuned", "chunk_pct", "waves"]}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "countpairs.h"',
              'int main(void) {']
     for st, fs in fields.items():

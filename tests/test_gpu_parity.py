@@ -184,6 +184,58 @@ def test_lattice_edge_ties(native, prec, mode):
         assert g.stats["rechecks"] > 0
 
 
+@pytest.mark.parametrize("e0", [0.0, 0.25])
+def test_coincident_points(native, e0):
+    """Coincident distinct points (separation 0) on a grid without wrapped
+    cells: with a first edge of 0 they land in bin 0 (half-open from 0), with
+    a positive first edge they are dropped.  Binary32 estimates of a zero
+    separation carry rounding of either sign, so near E_0 = 0 they must still
+    land in bin 0; lattice partners planted exactly on edges (and on pi edges)
+    force binary64 rechecks.  xi (weighted and not), w_p and cross, both
+    precisions, against the oracle."""
+    rng = np.random.Generator(np.random.PCG64(71))
+    q = 2.0 ** -6
+    lq = int(420.0 / q)
+    k = rng.integers(0, lq, (20_000, 3))
+    # partners at edge distances (axis and 3-4-5 offsets) and exact duplicates
+    base = k[rng.integers(0, len(k), 600)]
+    offs = np.array([[32, 0, 0], [0, 64, 0], [0, 0, 128], [3 * 64, 4 * 64, 0],
+                     [0, 3 * 128, 4 * 128], [640, 0, 0], [0, 0, 64 * 5]])
+    extra = (base[:, None, :] + offs[None]).reshape(-1, 3) % lq
+    dups = k[rng.integers(0, len(k), 500)]
+    kk = np.concatenate([k, extra, dups], 0)
+    w = rng.integers(1, 8, len(kk)) * 0.25
+    cat = synth.Catalog(*(np.ascontiguousarray(kk[:, a] * q) for a in range(3)), w=w)
+    edges = np.array([e0, 0.5, 1.0, 2.0, 3.0, 5.0, 10.0, 20.0])
+    d = native.to_device(cat)
+    ref = oracle.xi(cat, edges, periodic=True, box=420.0)
+    refw = oracle.wp(cat, edges, 16.0, 16, periodic=True, box=420.0)
+    other = synth.Catalog(cat.x[:5000].copy(), cat.y[:5000].copy(), cat.z[:5000].copy(),
+                          cat.w[:5000].copy())
+    refc = oracle.xi(cat, edges, periodic=True, box=420.0, other=other)
+    if e0 == 0.0:
+        # each duplicate adds at least one coincident pair, counted both ways
+        assert ref.npairs[0] >= 2 * len(dups)
+    for prec in ("fp64", "fp32"):
+        _say("coincident", e0, prec)
+        g = native.countpairs_xi(d, edges, precision=prec, periodic=True, boxsize=420.0)
+        _check(g, ref, prec=prec)
+        assert min(g.stats["grid"]) > 1
+        if prec == "fp32":
+            assert g.stats["rechecks"] > 0
+        g = native.countpairs_xi(d, edges, precision=prec, periodic=True, boxsize=420.0,
+                                 need_ravg=True)
+        _check(g, ref, weighted=True, prec=prec)
+        g = native.countpairs_wp(d, edges, 16.0, 16, precision=prec, periodic=True,
+                                 boxsize=420.0)
+        _check(g, refw, prec=prec)
+        if prec == "fp32":
+            assert g.stats["rechecks"] > 0
+        g = native.countpairs_cross(d, native.to_device(other), edges, precision=prec,
+                                    periodic=True, boxsize=420.0)
+        _check(g, refc, prec=prec)
+
+
 def test_full_box_total(native):
     """R_max beyond half the box: per-pair minimum image, N(N-1) in total."""
     cat = synth.uniform(3000, 420.0, seed=3)
@@ -529,22 +581,56 @@ def test_plan_graph_replays(native):
 
 
 def test_autotuned_refine_same_counts(native, tmp_path, monkeypatch):
-    monkeypatch.setenv("CP_AUTOTUNE_CACHE", str(tmp_path / "at.json"))
+    """refine = 0 through the C ABI: the library times candidate settings on
+    the call's data (refine factors, work-chunk target, waves per workgroup),
+    writes its JSON cache, reuses the choice on the next call of the same
+    signature; counts equal the oracle either way.  CP_AUTOTUNE=0 gives the
+    library defaults; an explicit refine is used as given."""
+    import json
+    cache = tmp_path / "at.json"
+    monkeypatch.setenv("CP_AUTOTUNE_CACHE", str(cache))
     cat = synth.clustered(40_000, 800, 1.5, 420.0, seed=12, weights=True)
     edges = synth.log_edges(0.1, 25.0, 14)
     d = native.to_device(cat)
     ref = oracle.xi(cat, edges, periodic=True, box=420.0)
-    g = native.countpairs_xi(d, edges, periodic=True, boxsize=420.0, refine="auto",
-                             need_ravg=True)
+    refw = oracle.wp(cat, edges, 40.0, 40, periodic=True, box=420.0)
+    _say("autotune xi")
+    g = native.countpairs_xi(d, edges, periodic=True, boxsize=420.0, need_ravg=True)
     _check(g, ref, weighted=True)
-    g = native.countpairs_wp(d, edges, 40.0, 40, periodic=True, boxsize=420.0, refine="auto")
-    _check(g, oracle.wp(cat, edges, 40.0, 40, periodic=True, box=420.0))
-    plan = native.Plan([d, native.to_device(synth.clustered(30_000, 600, 2.0, 420.0, seed=13))],
-                       xi_edges=edges, periodic=True, boxsize=420.0, refine="auto")
+    assert g.stats["tuned"] == "tuned", g.stats
+    text = cache.read_text()
+    json.loads(text)                          # the cache file is valid JSON
+    entries = [l for l in text.splitlines() if l.strip().startswith('"xi/')]
+    assert len(entries) == 1 and "/w/p/" in entries[0]
+    assert '"refine": [' in entries[0] and '"chunk_pct": ' in entries[0]
+    g2 = native.countpairs_xi(d, edges, periodic=True, boxsize=420.0, need_ravg=True)
+    _check(g2, ref, weighted=True)
+    assert g2.stats["tuned"] == "cached"
+    assert g2.stats["refine"] == g.stats["refine"] and g2.stats["chunk_pct"] == g.stats["chunk_pct"]
+    _say("autotune wp")
+    g = native.countpairs_wp(d, edges, 40.0, 40, periodic=True, boxsize=420.0)
+    _check(g, refw, prec="fp32")
+    assert g.stats["tuned"] == "tuned"
+    monkeypatch.setenv("CP_AUTOTUNE", "0")
+    g = native.countpairs_xi(d, edges, periodic=True, boxsize=420.0, precision="fp64")
+    _check(g, ref)
+    assert g.stats["tuned"] == "default" and g.stats["refine"] == [2, 2, 2]
+    monkeypatch.delenv("CP_AUTOTUNE")
+    g = native.countpairs_xi(d, edges, periodic=True, boxsize=420.0, refine=(3, 3, 1))
+    _check(g, ref)
+    assert g.stats["tuned"] == "given" and g.stats["refine"] == [3, 3, 1]
+    _say("autotune plan")
+    other = synth.clustered(30_000, 600, 2.0, 420.0, seed=13)
+    plan = native.Plan([d, native.to_device(other)], xi_edges=edges, wp_edges=edges, pimax=40.0,
+                       npibins=40, periodic=True, boxsize=420.0)
     plan.execute()
-    xi, _ = plan.results()
-    assert (xi[0] == ref.npairs).all()
+    xi, wp = plan.results()
+    sx, sw = plan.stats()
+    assert sx["tuned"] == "tuned" and sw["tuned"] == "tuned"
+    assert (xi[0] == ref.npairs).all() and (wp[0] == refw.npairs).all()
+    assert (xi[1] == oracle.xi(other, edges, periodic=True, box=420.0).npairs).all()
     plan.close()
+    assert any(l.strip().startswith('"plan:') for l in cache.read_text().splitlines())
 
 
 def test_caller_workspace(native):
