@@ -23,19 +23,16 @@ __global__ void k_bbox_final(const double *part, int nblk, double *out);
 __global__ void k_fill_i32(int *p, int64_t n, int v);
 __global__ void k_fill_u64(unsigned long long *p, int64_t n);
 __global__ void k_fill_f64(double *p, int64_t n);
-struct ScanSeg {
-  int64_t in_off;
-  int64_t out_off;
-  int64_t len;
-};
-__global__ void k_scan_segments(const int *in, int *out, const ScanSeg *segs);
+__global__ void k_scan_sums(const int *in, const ScanSeg *segs, int nseg, int *tsum);
+__global__ void k_scan_apply(const int *in, int *out, const ScanSeg *segs, int nseg,
+                             const int *tsum);
 __global__ void k_assign(const PointsDev *pts, const GridGeom *geom, int *cell_count, int *cid,
                          int *rank, int *err);
 __global__ void k_group(const PointsDev *pts, const GridGeom *geom, const int *cstart,
                         const int *cid, const int *rank, double4 *grp);
-__global__ void k_cellfin(const GridGeom *geom, int nmock, const int *cstart, const double4 *grp,
-                          double4 *pos, float4 *strm, CellBox *cbox, const int64_t *cell_prefix,
-                          int mode);
+__global__ void k_cellsort(const GridGeom *geom, int nmock, const int *cstart, const double4 *grp,
+                           double4 *pos, float4 *strm, CellBox *cbox, const int64_t *win_prefix,
+                           int mode);
 __global__ void k_tiles(const GridGeom *geom, int nmock, const int *cstart, const int *maxspan,
                         const int64_t *col_prefix, int *colcnt, const int *coloff, Tile *tiles,
                         int emit);
@@ -426,6 +423,7 @@ struct Carver {
 // Device buffers of one gridded point set.
 struct SetBufs {
   int *ccount, *cstart, *cid, *rank, *colcnt, *coloff;
+  int *tsum;            // tile totals of the segmented scans
   double4 *pos, *grp;   // grp: points grouped by cell before the z order
   float4 *strm;
   CellBox *cbox;
@@ -434,8 +432,9 @@ struct SetBufs {
 
 static void carve_set(Carver &cv, SetBufs &S, int64_t n, int64_t ncell, int64_t ncol,
                       bool want_tiles, int64_t maxtiles) {
-  S.ccount = cv.take<int>(ncell);
+  S.ccount = cv.take<int>(ncell * kCountStride);
   S.cstart = cv.take<int>(ncell + 1);
+  S.tsum = cv.take<int>(std::max(scan_tiles(ncell), scan_tiles(ncol)));
   S.cid = cv.take<int>(n > 0 ? n : 1);
   S.rank = cv.take<int>(n > 0 ? n : 1);
   // +8 records: the pair kernels prefetch scalar loads past a cell's end
@@ -458,7 +457,7 @@ struct Smalls {
   GridGeom geom[2];
   PointsDev pts[2];
   ScanSeg seg[3];
-  int64_t cell_prefix[2];
+  int64_t win_prefix[2][2];   // z-order windows of set 1 and set 2
   int64_t col_prefix[2];
   int maxspan[2];
   int ntiles_dummy;
@@ -535,29 +534,35 @@ static int64_t max_tiles_bound(int64_t n, int64_t ncell, int64_t ncol) {
 static int launch_build(hipStream_t st, const PointsDev *d_pts, const GridGeom *d_geom,
                         const SetBufs &S, int64_t n, int64_t ncell, int64_t ncol, int mode,
                         const ScanSeg *d_seg_cells, const ScanSeg *d_seg_cols,
-                        const int64_t *d_cell_prefix, const int64_t *d_col_prefix,
+                        const int64_t *d_win_prefix, const int64_t *d_col_prefix,
                         const int *d_maxspan, int *d_err, bool tiles) {
-  const int fb = (int)std::min<int64_t>(std::max<int64_t>((ncell + 255) / 256, 1), 4096);
+  const int fb = (int)std::min<int64_t>(std::max<int64_t>((ncell * kCountStride + 255) / 256, 1), 4096);
   (void)hipGetLastError();
-  hipLaunchKernelGGL(k_fill_i32, dim3(fb), dim3(256), 0, st, S.ccount, ncell, 0);
+  hipLaunchKernelGGL(k_fill_i32, dim3(fb), dim3(256), 0, st, S.ccount, ncell * kCountStride, 0);
   const int ab = (int)std::min<int64_t>(std::max<int64_t>((n + 255) / 256, 1), 8192);
   if (n > 0)
     hipLaunchKernelGGL(k_assign, dim3(ab, 1), dim3(256), 0, st, d_pts, d_geom, S.ccount, S.cid,
                        S.rank, d_err);
-  hipLaunchKernelGGL(k_scan_segments, dim3(1), dim3(1024), 0, st, S.ccount, S.cstart,
-                     d_seg_cells);
+  const unsigned sc = (unsigned)scan_tiles(ncell);
+  hipLaunchKernelGGL(k_scan_sums, dim3(sc), dim3(256), 0, st, S.ccount, d_seg_cells, 1, S.tsum);
+  hipLaunchKernelGGL(k_scan_apply, dim3(sc), dim3(256), 0, st, S.ccount, S.cstart, d_seg_cells, 1,
+                     S.tsum);
   if (n > 0)
     hipLaunchKernelGGL(k_group, dim3(ab, 1), dim3(256), 0, st, d_pts, d_geom, S.cstart, S.cid,
                        S.rank, S.grp);
-  const int cb = (int)std::min<int64_t>(std::max<int64_t>((ncell + 3) / 4, 1), 16384);
-  hipLaunchKernelGGL(k_cellfin, dim3(cb), dim3(256), 0, st, d_geom, 1, S.cstart, S.grp, S.pos,
-                     S.strm, S.cbox, d_cell_prefix, mode);
+  const int64_t nwin = (n + kSortWin - 1) / kSortWin;
+  const int cb = (int)std::min<int64_t>(std::max<int64_t>((nwin + 3) / 4, 1), 16384);
+  if (n > 0)
+    hipLaunchKernelGGL(k_cellsort, dim3(cb), dim3(256), 0, st, d_geom, 1, S.cstart, S.grp, S.pos,
+                       S.strm, S.cbox, d_win_prefix, mode);
   if (tiles) {
     const int tb = (int)std::min<int64_t>(std::max<int64_t>((ncol + 3) / 4, 1), 16384);
     hipLaunchKernelGGL(k_tiles, dim3(tb), dim3(256), 0, st, d_geom, 1, S.cstart, d_maxspan,
                        d_col_prefix, S.colcnt, S.coloff, S.tiles, 0);
-    hipLaunchKernelGGL(k_scan_segments, dim3(1), dim3(1024), 0, st, S.colcnt, S.coloff,
-                       d_seg_cols);
+    const unsigned tc = (unsigned)scan_tiles(ncol);
+    hipLaunchKernelGGL(k_scan_sums, dim3(tc), dim3(256), 0, st, S.colcnt, d_seg_cols, 1, S.tsum);
+    hipLaunchKernelGGL(k_scan_apply, dim3(tc), dim3(256), 0, st, S.colcnt, S.coloff, d_seg_cols,
+                       1, S.tsum);
     hipLaunchKernelGGL(k_tiles, dim3(tb), dim3(256), 0, st, d_geom, 1, S.cstart, d_maxspan,
                        d_col_prefix, S.colcnt, S.coloff, S.tiles, 1);
   }
@@ -1048,10 +1053,12 @@ static int run(const Call &c, uint64_t *npairs, double *wsum, double *ravg) {
   hs.geom[1] = to_dev_geom(g, o.periodic != 0, o.boxsize, 0, 0, 0, p2.n, 0);
   hs.pts[0] = pd[0];
   hs.pts[1] = pd[1];
-  hs.seg[0] = {0, 0, ncell};
-  hs.seg[1] = {0, 0, ncol};
-  hs.cell_prefix[0] = 0;
-  hs.cell_prefix[1] = ncell;
+  hs.seg[0] = {0, 0, ncell, 0, kCountStride};
+  hs.seg[1] = {0, 0, ncol, 0, 1};
+  hs.win_prefix[0][0] = 0;
+  hs.win_prefix[0][1] = (p1.n + kSortWin - 1) / kSortWin;
+  hs.win_prefix[1][0] = 0;
+  hs.win_prefix[1][1] = (p2.n + kSortWin - 1) / kSortWin;
   hs.col_prefix[0] = 0;
   hs.col_prefix[1] = ncol;
   hs.maxspan[0] = g.maxspan;
@@ -1085,12 +1092,12 @@ static int run(const Call &c, uint64_t *npairs, double *wsum, double *ravg) {
 
   // ---- cell build
   rc = launch_build(st, &d_sm->pts[0], &d_sm->geom[0], S1, p1.n, ncell, ncol, c.mode,
-                    &d_sm->seg[0], &d_sm->seg[1], d_sm->cell_prefix, d_sm->col_prefix,
+                    &d_sm->seg[0], &d_sm->seg[1], d_sm->win_prefix[0], d_sm->col_prefix,
                     d_sm->maxspan, d_err, true);
   if (rc) return rc;
   if (!autoc) {
     rc = launch_build(st, &d_sm->pts[1], &d_sm->geom[1], S2, p2.n, ncell, ncol, c.mode,
-                      &d_sm->seg[0], &d_sm->seg[1], d_sm->cell_prefix, d_sm->col_prefix,
+                      &d_sm->seg[0], &d_sm->seg[1], d_sm->win_prefix[1], d_sm->col_prefix,
                       d_sm->maxspan, d_err, false);
     if (rc) return rc;
   }
@@ -1416,13 +1423,13 @@ struct Batch {
   int64_t ncell = 0, ncol = 0, ncell_tot = 0, ncol_tot = 0, npts_tot = 0, maxtiles = 0;
   std::vector<GridGeom> geoms;
   std::vector<ScanSeg> segs;      // nmock cell segments, then 1 column segment
-  std::vector<int64_t> cell_prefix, col_prefix;
+  std::vector<int64_t> win_prefix, col_prefix;
   std::vector<int> maxspan;
   // device
   GridGeom *d_geom = nullptr;
   PointsDev *d_pts = nullptr;
   ScanSeg *d_segs = nullptr;
-  int64_t *d_cell_prefix = nullptr, *d_col_prefix = nullptr;
+  int64_t *d_win_prefix = nullptr, *d_col_prefix = nullptr;
   int *d_maxspan = nullptr;
   SetBufs S{};
   uint2 *d_t32 = nullptr, *d_t64 = nullptr;
@@ -1480,15 +1487,15 @@ static int batch_prepare(cp_plan &pl, Batch &b, int mode, int prec, const double
   b.ncol = (int64_t)b.g.n[0] * b.g.n[1];
   b.geoms.clear();
   b.segs.clear();
-  b.cell_prefix.assign(1, 0);
+  b.win_prefix.assign(1, 0);
   b.col_prefix.assign(1, 0);
   b.maxspan.clear();
   int64_t pb = 0;
   for (int m = 0; m < pl.nmock; m++) {
     const int64_t cbase = b.ncell * m, sbase = (b.ncell + 1) * m, colbase = b.ncol * m;
     b.geoms.push_back(to_dev_geom(b.g, true, o.boxsize, pb, cbase, sbase, pl.n[m], colbase));
-    b.segs.push_back({cbase, sbase, b.ncell});
-    b.cell_prefix.push_back(b.ncell * (m + 1));
+    b.segs.push_back({cbase, sbase, b.ncell, scan_tiles(b.ncell) * m, kCountStride});
+    b.win_prefix.push_back(b.win_prefix.back() + (pl.n[m] + kSortWin - 1) / kSortWin);
     b.col_prefix.push_back(b.ncol * (m + 1));
     b.maxspan.push_back(b.g.maxspan);
     pb += pl.n[m];
@@ -1496,7 +1503,7 @@ static int batch_prepare(cp_plan &pl, Batch &b, int mode, int prec, const double
   b.npts_tot = pb;
   b.ncell_tot = b.ncell * pl.nmock;
   b.ncol_tot = b.ncol * pl.nmock;
-  b.segs.push_back({0, 0, b.ncol_tot});
+  b.segs.push_back({0, 0, b.ncol_tot, 0, 1});
   b.maxtiles = max_tiles_bound(b.npts_tot, b.ncell_tot, b.ncol_tot);
   const LdsLayout LY = lds_layout(mode, b.prec, 0, (int)b.B.t32.e.size(),
                                        (int)b.B.t64.e.size(), b.nb, b.npi);
@@ -1511,11 +1518,12 @@ static void batch_carve(Carver &cv, cp_plan &pl, Batch &b) {
   b.d_geom = cv.take<GridGeom>(nm);
   b.d_pts = cv.take<PointsDev>(nm);
   b.d_segs = cv.take<ScanSeg>(nm + 1);
-  b.d_cell_prefix = cv.take<int64_t>(nm + 1);
+  b.d_win_prefix = cv.take<int64_t>(nm + 1);
   b.d_col_prefix = cv.take<int64_t>(nm + 1);
   b.d_maxspan = cv.take<int>(nm);
   // cell_start needs ncell + 1 per catalogue
-  b.S.ccount = cv.take<int>(b.ncell_tot);
+  b.S.ccount = cv.take<int>(b.ncell_tot * kCountStride);
+  b.S.tsum = cv.take<int>(std::max(scan_tiles(b.ncell) * nm, scan_tiles(b.ncol_tot)));
   b.S.cstart = cv.take<int>(b.ncell_tot + nm);
   b.S.cid = cv.take<int>(std::max<int64_t>(b.npts_tot, 1));
   b.S.rank = cv.take<int>(std::max<int64_t>(b.npts_tot, 1));
@@ -1544,7 +1552,7 @@ static int batch_upload(cp_plan &pl, Batch &b) {
   HIPCHK(hipMemcpy(b.d_geom, b.geoms.data(), sizeof(GridGeom) * nm, hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(b.d_pts, pl.pts.data(), sizeof(PointsDev) * nm, hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(b.d_segs, b.segs.data(), sizeof(ScanSeg) * (nm + 1), hipMemcpyHostToDevice));
-  HIPCHK(hipMemcpy(b.d_cell_prefix, b.cell_prefix.data(), 8 * (nm + 1), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(b.d_win_prefix, b.win_prefix.data(), 8 * (nm + 1), hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(b.d_col_prefix, b.col_prefix.data(), 8 * (nm + 1), hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(b.d_maxspan, b.maxspan.data(), 4 * nm, hipMemcpyHostToDevice));
   if (!b.B.t32.e.empty())
@@ -1608,25 +1616,31 @@ static int batch_enqueue(cp_plan &pl, Batch &b, hipStream_t st) {
   auto blocks = [](int64_t n, int per, int cap) {
     return (int)std::min<int64_t>(std::max<int64_t>((n + per - 1) / per, 1), cap);
   };
-  hipLaunchKernelGGL(k_fill_i32, dim3(blocks(b.ncell_tot, 256, 8192)), dim3(256), 0, st,
-                     b.S.ccount, b.ncell_tot, 0);
+  hipLaunchKernelGGL(k_fill_i32, dim3(blocks(b.ncell_tot * kCountStride, 256, 8192)), dim3(256), 0,
+                     st, b.S.ccount, b.ncell_tot * kCountStride, 0);
   hipLaunchKernelGGL(k_fill_u64, dim3(blocks((int64_t)b.nout * nm, 256, 1024)), dim3(256), 0, st,
                      b.d_hist, (int64_t)b.nout * nm);
   hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, b.d_stats, (int64_t)kStatWords);
   hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, b.d_err, (int64_t)1, 0);
   hipLaunchKernelGGL(k_assign, dim3(blocks(pl.maxn, 256, 4096), nm), dim3(256), 0, st, b.d_pts,
                      b.d_geom, b.S.ccount, b.S.cid, b.S.rank, b.d_err);
-  hipLaunchKernelGGL(k_scan_segments, dim3(nm), dim3(1024), 0, st, b.S.ccount, b.S.cstart,
-                     b.d_segs);
+  const unsigned sc = (unsigned)(scan_tiles(b.ncell) * nm);
+  hipLaunchKernelGGL(k_scan_sums, dim3(sc), dim3(256), 0, st, b.S.ccount, b.d_segs, nm, b.S.tsum);
+  hipLaunchKernelGGL(k_scan_apply, dim3(sc), dim3(256), 0, st, b.S.ccount, b.S.cstart, b.d_segs,
+                     nm, b.S.tsum);
   hipLaunchKernelGGL(k_group, dim3(blocks(pl.maxn, 256, 4096), nm), dim3(256), 0, st, b.d_pts,
                      b.d_geom, b.S.cstart, b.S.cid, b.S.rank, b.S.grp);
-  hipLaunchKernelGGL(k_cellfin, dim3(blocks(b.ncell_tot, 4, 65536)), dim3(256), 0, st, b.d_geom,
-                     nm, b.S.cstart, b.S.grp, b.S.pos, b.S.strm, b.S.cbox, b.d_cell_prefix, b.mode);
+  hipLaunchKernelGGL(k_cellsort, dim3(blocks(b.win_prefix[nm], 4, 65536)), dim3(256), 0, st,
+                     b.d_geom, nm, b.S.cstart, b.S.grp, b.S.pos, b.S.strm, b.S.cbox, b.d_win_prefix,
+                     b.mode);
   const int tb = blocks(b.ncol_tot, 4, 65536);
   hipLaunchKernelGGL(k_tiles, dim3(tb), dim3(256), 0, st, b.d_geom, nm, b.S.cstart, b.d_maxspan,
                      b.d_col_prefix, b.S.colcnt, b.S.coloff, b.S.tiles, 0);
-  hipLaunchKernelGGL(k_scan_segments, dim3(1), dim3(1024), 0, st, b.S.colcnt, b.S.coloff,
-                     b.d_segs + nm);
+  const unsigned tcol = (unsigned)scan_tiles(b.ncol_tot);
+  hipLaunchKernelGGL(k_scan_sums, dim3(tcol), dim3(256), 0, st, b.S.colcnt, b.d_segs + nm, 1,
+                     b.S.tsum);
+  hipLaunchKernelGGL(k_scan_apply, dim3(tcol), dim3(256), 0, st, b.S.colcnt, b.S.coloff,
+                     b.d_segs + nm, 1, b.S.tsum);
   hipLaunchKernelGGL(k_tiles, dim3(tb), dim3(256), 0, st, b.d_geom, nm, b.S.cstart, b.d_maxspan,
                      b.d_col_prefix, b.S.colcnt, b.S.coloff, b.S.tiles, 1);
   return launch_pairs(st, b.mode, b.prec, 0, b.P, b.lds, b.nwaves);

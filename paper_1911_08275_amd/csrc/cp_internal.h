@@ -15,6 +15,7 @@ constexpr int kMaxBins = 60;        // separation bins; slots 0 and nb+1 are tra
                                     // slot + 1 must fit the 6-bit table code
 constexpr int kMaxPiBins = 256;
 constexpr int kZSortMax = 4096;   // cells up to this many points are z-sorted
+constexpr int kSortWin = 128;     // grouped positions per wave of the z-order pass
 // Work queues of the pair kernel: one per XCD (workgroups are dealt to the
 // MI355X's 8 XCDs round-robin, so blockIdx.x % 8 names the XCD), each
 // holding a contiguous, hence spatially compact, share of the items; a wave
@@ -33,6 +34,25 @@ constexpr int kStatWords = 5 + kQueues * kQStride;
 constexpr int kMaxChunks = 32;
 constexpr int kStaticLds = 256;  // LDS the pair kernel declares statically (queue mask)
 constexpr int kWStripe = 8;       // copies of each weight sum per wave (lane & 7)
+
+// Cell counters of the build: one per cell, kCountStride ints apart.
+constexpr int kCountStride = 1;
+
+// Segmented exclusive scans (cell counts -> cell starts, tile counts -> tile
+// offsets): out[out_off + k] = sum of the first k of the segment's len values
+// in[(in_off + j) * stride], and out[out_off + len] = their total.  Tiles of
+// kScanTile values, numbered across the segments of one launch from tile0.
+constexpr int kScanTile = 4096;
+struct ScanSeg {
+  int64_t in_off;
+  int64_t out_off;
+  int64_t len;
+  int64_t tile0;
+  int64_t stride;
+};
+__host__ __device__ inline int64_t scan_tiles(int64_t len) {
+  return len > 0 ? (len + kScanTile - 1) / kScanTile : 1;
+}
 
 // Sets the calling thread's countpairs_last_error text and returns code.
 int report_error(int code, const char *msg);

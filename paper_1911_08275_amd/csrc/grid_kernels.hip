@@ -9,6 +9,7 @@
 #include "cp_internal.h"
 
 #include <float.h>
+#include <limits.h>
 
 namespace cp {
 
@@ -94,68 +95,125 @@ __global__ void k_fill_f64(double *p, int64_t n) {
     p[i] = 0.0;
 }
 
-struct ScanSeg {
-  int64_t in_off;
-  int64_t out_off;
-  int64_t len;
-};
+// Segment of launch tile b (segments ordered by tile0).
+__device__ inline int scan_segment(const ScanSeg *segs, int nseg, int64_t b) {
+  int lo = 0, hi = nseg - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (segs[mid].tile0 <= b) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
 
-// Exclusive scan of one segment per block: out[0..len] with out[len] = total.
-// Each of the 1024 threads sums a contiguous chunk, the block scans the
-// chunk sums, then each thread writes its chunk.
-__global__ __launch_bounds__(1024) void k_scan_segments(const int *in, int *out,
-                                                        const ScanSeg *segs) {
-  // Tiles of 4096 values: 4 consecutive values per thread, a shuffle scan
-  // inside each wave, the 16 wave totals scanned by wave 0, and a running
-  // carry from tile to tile.
-  const ScanSeg S = segs[blockIdx.x];
-  const int *src = in + S.in_off;
-  int *dst = out + S.out_off;
+// Values of one scan tile held by thread tid: four runs of four consecutive
+// values, run g at tile offset g * 1024 + 4 tid (coalesced), zero past len.
+// Loads use clamped indices so that all sixteen are in flight together.
+__device__ inline void scan_load(const int *in, const ScanSeg &S, int64_t base, int tid,
+                                 int (&v)[4][4]) {
+#pragma unroll
+  for (int g = 0; g < 4; g++)
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      const int64_t j = base + g * 1024 + 4 * tid + k;
+      v[g][k] = in[(S.in_off + min(j, S.len - 1)) * S.stride];
+    }
+#pragma unroll
+  for (int g = 0; g < 4; g++)
+#pragma unroll
+    for (int k = 0; k < 4; k++)
+      if (base + g * 1024 + 4 * tid + k >= S.len) v[g][k] = 0;
+}
+
+__device__ inline int block_sum256(int x, int *red) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = x;
+  __syncthreads();
+  const int t = (red[0] + red[1]) + (red[2] + red[3]);
+  __syncthreads();
+  return t;
+}
+
+// Pass 1 of the segmented scans: the total of every tile (one block each).
+__global__ __launch_bounds__(256) void k_scan_sums(const int *in, const ScanSeg *segs, int nseg,
+                                                   int *tsum) {
+  __shared__ int red[4];
+  const int64_t b = blockIdx.x;
+  const ScanSeg S = segs[scan_segment(segs, nseg, b)];
+  if (S.len == 0) {
+    if (threadIdx.x == 0) tsum[b] = 0;
+    return;
+  }
+  int v[4][4];
+  scan_load(in, S, (b - S.tile0) * kScanTile, threadIdx.x, v);
+  int x = 0;
+#pragma unroll
+  for (int g = 0; g < 4; g++) x += (v[g][0] + v[g][1]) + (v[g][2] + v[g][3]);
+  x = block_sum256(x, red);
+  if (threadIdx.x == 0) tsum[b] = x;
+}
+
+// Pass 2: every tile scanned at once (one block each), starting from the sum
+// of its segment's earlier tiles; the segment's last tile writes the total.
+__global__ __launch_bounds__(256) void k_scan_apply(const int *in, int *out, const ScanSeg *segs,
+                                                    int nseg, const int *tsum) {
+  __shared__ int red[4];
   __shared__ int wsum[16];
+  const int64_t b = blockIdx.x;
+  const ScanSeg S = segs[scan_segment(segs, nseg, b)];
+  int *dst = out + S.out_off;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  int carry = 0;
-  // the next tile's values are loaded before this tile's barriers, so the
-  // memory latency overlaps the scan
-  int nv[4];
+  if (S.len == 0) {
+    if (tid == 0) dst[0] = 0;
+    return;
+  }
+  const int64_t base = (b - S.tile0) * kScanTile;
+  int v[4][4];
+  scan_load(in, S, base, tid, v);
+  int c = 0;
+  for (int64_t u = S.tile0 + tid; u < b; u += 256) c += tsum[u];
+  const int carry = block_sum256(c, red);
+  int loc[4], x[4];
 #pragma unroll
-  for (int k = 0; k < 4; k++) nv[k] = 4 * (int64_t)tid + k < S.len ? src[4 * tid + k] : 0;
-  for (int64_t t0 = 0; t0 < S.len; t0 += 4096) {
-    const int64_t i0 = t0 + 4 * (int64_t)tid;
-    int v[4];
+  for (int g = 0; g < 4; g++) {
+    loc[g] = (v[g][0] + v[g][1]) + (v[g][2] + v[g][3]);
+    x[g] = loc[g];
+  }
 #pragma unroll
-    for (int k = 0; k < 4; k++) v[k] = nv[k];
-    const int64_t n0 = i0 + 4096;
+  for (int off = 1; off < 64; off <<= 1) {
 #pragma unroll
-    for (int k = 0; k < 4; k++) nv[k] = n0 + k < S.len ? src[n0 + k] : 0;
-    const int loc = (v[0] + v[1]) + (v[2] + v[3]);
-    int x = loc;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-      const int y = __shfl_up(x, off);
-      if (lane >= off) x += y;
+    for (int g = 0; g < 4; g++) {
+      const int y = __shfl_up(x[g], off);
+      if (lane >= off) x[g] += y;
     }
-    if (lane == 63) wsum[w] = x;
-    __syncthreads();
-    if (w == 0) {
-      int t = lane < 16 ? wsum[lane] : 0;
+  }
+  if (lane == 63) {
 #pragma unroll
-      for (int off = 1; off < 16; off <<= 1) {
-        const int y = __shfl_up(t, off);
-        if (lane >= off) t += y;
-      }
-      if (lane < 16) wsum[lane] = t;
+    for (int g = 0; g < 4; g++) wsum[g * 4 + w] = x[g];
+  }
+  __syncthreads();
+  if (w == 0) {
+    int t = lane < 16 ? wsum[lane] : 0;
+#pragma unroll
+    for (int off = 1; off < 16; off <<= 1) {
+      const int y = __shfl_up(t, off);
+      if (lane >= off) t += y;
     }
-    __syncthreads();
-    int run = carry + (w > 0 ? wsum[w - 1] : 0) + (x - loc);
+    if (lane < 16) wsum[lane] = t;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int g = 0; g < 4; g++) {
+    const int q = g * 4 + w;
+    int run = carry + (q > 0 ? wsum[q - 1] : 0) + (x[g] - loc[g]);
+    const int64_t i0 = base + g * 1024 + 4 * (int64_t)tid;
 #pragma unroll
     for (int k = 0; k < 4; k++) {
       if (i0 + k < S.len) dst[i0 + k] = run;
-      run += v[k];
+      run += v[g][k];
     }
-    carry += wsum[15];
-    __syncthreads();
   }
-  if (tid == 0) dst[S.len] = carry;
+  if (tid == 0 && base + kScanTile >= S.len) dst[S.len] = carry + wsum[15];
 }
 
 // --------------------------------------------------------- cell assignment
@@ -183,17 +241,17 @@ __global__ __launch_bounds__(256) void k_assign(const PointsDev *pts, const Grid
     if (P.w && !isfinite(P.w[i])) bad |= ERRF_NONFINITE;
     int cell = (c[0] * G.n[1] + c[1]) * G.n[2] + c[2];
     cid[G.pbase + i] = cell;
-    rank[G.pbase + i] = atomicAdd(&cell_count[G.cbase + cell], 1);
+    rank[G.pbase + i] = atomicAdd(&cell_count[(G.cbase + cell) * kCountStride], 1);
   }
   if (bad) atomicOr(err, bad);
 }
 
 // Cell order, z ascending inside each cell (Section 2.1 contiguous per-cell
-// storage and z-sorted cells, used by the late entry / early exit of Section 2.2).  k_group
-// copies every point's (x, y, z, w) to its cell's range in the atomic order;
-// k_cellfin, one wave per cell, ranks the cell's points by z (ties by grouped
-// position, so the ranks form a permutation), writes them in that order
-// together with their binary32 stream records, and takes the cell's bounding
+// storage and z-sorted cells, used by the late entry / early exit of Section
+// 2.2).  k_group copies every point's (x, y, z, w) to its cell's range in the
+// atomic order; k_cellsort ranks each point by z inside its cell (ties by
+// grouped position, so the ranks form a permutation), writes it in that order
+// together with its binary32 stream record, and takes the cell's bounding
 // box.  Cells above kZSortMax points keep the grouped order.
 __global__ __launch_bounds__(256) void k_group(const PointsDev *pts, const GridGeom *geom,
                                                const int *cstart, const int *cid,
@@ -212,10 +270,8 @@ __global__ __launch_bounds__(256) void k_group(const PointsDev *pts, const GridG
 // Stream record of a point in the frame of its own cell (centre O):
 //   xi: (-2 px, -2 py, -2 pz, |p|^2)      wp: (-2 px, -2 py, pz, px^2 + py^2)
 // with p = fl32(x - O).
-__device__ inline float4 stream_record(const GridGeom &G, int cell, const double4 &v, int mode) {
-  const int cz = cell % G.n[2];
-  const int cy = (cell / G.n[2]) % G.n[1];
-  const int cx = cell / (G.n[2] * G.n[1]);
+__device__ inline float4 stream_record(const GridGeom &G, int cx, int cy, int cz,
+                                       const double4 &v, int mode) {
   const float px = (float)(v.x - frame_origin(G, 0, cx));
   const float py = (float)(v.y - frame_origin(G, 1, cy));
   const float pz = (float)(v.z - frame_origin(G, 2, cz));
@@ -232,97 +288,261 @@ __device__ inline float4 stream_record(const GridGeom &G, int cell, const double
   return s;
 }
 
-constexpr int kZChunk = 256;    // z values staged in LDS per step, per wave
+// Each wave takes a window of kSortWin consecutive grouped positions of one
+// catalogue (kSortWin / 64 per lane).  A lane finds its point's cell from the
+// coordinates (the cell k_assign computed, by the same function) and the
+// cell's range [cb, ce) from the scanned counts; its z rank is the number of
+// cell members that precede it in (z, grouped position) order: members at
+// earlier positions with z <= its z, later ones with z < its z.  The wave
+// stages the z of every cell its window touches in its LDS slice, kSortStage
+// values at a time, and each lane scans its own cell's part of the stage.
+//
+// Bounding box: z from the ends of the z order (the lanes of rank 0 and
+// n - 1), x and y from a segmented min/max over consecutive positions (the
+// cells are contiguous runs) carried from block to block of the window; the
+// window holding a cell's first position owns it and, when the cell runs past
+// the window's end, reduces the rest of it too.  Every field of a box is
+// written by exactly one lane.  Cells above kZSortMax points keep the grouped
+// order, and their owner reduces all six extents over the whole cell.
+// Every window's wave is independent (no workgroup barrier).
+constexpr int kSortStage = 512;
 
-// NP points per lane: rank by a broadcast scan over the staged z values,
-// then write them (and their stream records) at b + rank; min/max update.
-template <int NP>
-__device__ inline void cellfin_pass(const GridGeom &G, int cell, const double4 *grp,
-                                    int64_t base, int n, int q0, int lane, double *zw,
-                                    double4 *pos, float4 *strm, int mode, double mn[3],
-                                    double mx[3]) {
-  double4 v[NP];
-  int kq[NP], r[NP];
-#pragma unroll
-  for (int p = 0; p < NP; p++) {
-    kq[p] = q0 + p * 64 + lane;
-    v[p] = kq[p] < n ? grp[base + kq[p]] : make_double4(0.0, 0.0, 0.0, 0.0);
-    r[p] = kq[p];
-  }
-  if (n <= kZSortMax) {
-#pragma unroll
-    for (int p = 0; p < NP; p++) r[p] = 0;
-    for (int c0 = 0; c0 < n; c0 += kZChunk) {
-      const int cnt = min(kZChunk, n - c0);
-      if (q0 == 0 || n > kZChunk) {   // (re)stage this chunk
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        for (int t = lane; t < cnt; t += 64) zw[t] = grp[base + c0 + t].z;
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-      }
-#pragma unroll 4
-      for (int t = 0; t < cnt; t++) {
-        const double zj = zw[t];
-#pragma unroll
-        for (int p = 0; p < NP; p++)
-          r[p] += (zj < v[p].z || (zj == v[p].z && c0 + t < kq[p])) ? 1 : 0;
-      }
-    }
-  }
-#pragma unroll
-  for (int p = 0; p < NP; p++) {
-    if (kq[p] < n) {
-      pos[base + r[p]] = v[p];
-      strm[base + r[p]] = stream_record(G, cell, v[p], mode);
-      mn[0] = fmin(mn[0], v[p].x); mx[0] = fmax(mx[0], v[p].x);
-      mn[1] = fmin(mn[1], v[p].y); mx[1] = fmax(mx[1], v[p].y);
-      mn[2] = fmin(mn[2], v[p].z); mx[2] = fmax(mx[2], v[p].z);
-    }
+// min/max of (x, y) in a/b folded over a segmented shuffle step
+__device__ inline void fold_xy(double (&a)[2], double (&b)[2], int off, bool take) {
+  double t[4];
+  t[0] = __shfl_up(a[0], off);
+  t[1] = __shfl_up(a[1], off);
+  t[2] = __shfl_up(b[0], off);
+  t[3] = __shfl_up(b[1], off);
+  if (take) {
+    a[0] = fmin(a[0], t[0]);
+    a[1] = fmin(a[1], t[1]);
+    b[0] = fmax(b[0], t[2]);
+    b[1] = fmax(b[1], t[3]);
   }
 }
 
-__global__ __launch_bounds__(256) void k_cellfin(const GridGeom *geom, int nmock,
-                                                 const int *cstart, const double4 *grp,
-                                                 double4 *pos, float4 *strm, CellBox *cbox,
-                                                 const int64_t *cell_prefix, int mode) {
-  __shared__ double zsh[4][kZChunk];
-  const int w = threadIdx.x >> 6;
-  const int wid = (int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6);
-  const int lane = threadIdx.x & 63;
-  double *zw = zsh[w];
-  const int64_t total = cell_prefix[nmock];
-  for (int64_t gc = wid; gc < total; gc += (int64_t)gridDim.x * (blockDim.x >> 6)) {
-    int lo = 0, hi = nmock - 1;
-    while (lo < hi) {
-      int mid = (lo + hi + 1) >> 1;
-      if (cell_prefix[mid] <= gc) lo = mid; else hi = mid - 1;
+__global__ __launch_bounds__(256) void k_cellsort(const GridGeom *geom, int nmock,
+                                                  const int *cstart, const double4 *grp,
+                                                  double4 *pos, float4 *strm, CellBox *cbox,
+                                                  const int64_t *win_prefix, int mode) {
+  constexpr int NP = kSortWin / 64;
+  __shared__ double szz[4][kSortStage];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  double *zz = szz[w];
+  const int64_t total = win_prefix[nmock];
+  const int64_t stride = (int64_t)gridDim.x * (blockDim.x >> 6);
+  for (int64_t gw = (int64_t)blockIdx.x * (blockDim.x >> 6) + w; gw < total; gw += stride) {
+    int m = 0, hi = nmock - 1;
+    while (m < hi) {
+      const int mid = (m + hi + 1) >> 1;
+      if (win_prefix[mid] <= gw) m = mid; else hi = mid - 1;
     }
-    const GridGeom &G = geom[lo];
-    const int c = (int)(gc - cell_prefix[lo]);
-    const int b = cstart[G.sbase + c], e = cstart[G.sbase + c + 1];
-    const int n = e - b;
-    const int64_t base = G.pbase + b;
-    double mn[3] = {DBL_MAX, DBL_MAX, DBL_MAX}, mx[3] = {-DBL_MAX, -DBL_MAX, -DBL_MAX};
-    if (n <= 64) {
-      cellfin_pass<1>(G, c, grp, base, n, 0, lane, zw, pos, strm, mode, mn, mx);
-    } else {
-      for (int q0 = 0; q0 < n; q0 += 4 * 64)
-        cellfin_pass<4>(G, c, grp, base, n, q0, lane, zw, pos, strm, mode, mn, mx);
+    const GridGeom &G = geom[m];
+    const int64_t pb = G.pbase;
+    const int *cs = cstart + G.sbase;
+    const int p0 = (int)(gw - win_prefix[m]) * kSortWin;
+    const int p1 = (int)min((int64_t)p0 + kSortWin, G.npts);
+    double4 v[NP];
+    int cell[NP], cb[NP], ce[NP], r[NP];
+    int rlo = INT_MAX, rhi = INT_MIN;
+    // loads at clamped positions, issued together (no branch between them)
+#pragma unroll
+    for (int k = 0; k < NP; k++) v[k] = grp[pb + min(p0 + k * 64 + lane, p1 - 1)];
+#pragma unroll
+    for (int k = 0; k < NP; k++) {
+      cell[k] = (cell_coord(G, 0, v[k].x) * G.n[1] + cell_coord(G, 1, v[k].y)) * G.n[2] +
+                cell_coord(G, 2, v[k].z);
+      cb[k] = cs[cell[k]];
+      ce[k] = cs[cell[k] + 1];
     }
+#pragma unroll
+    for (int k = 0; k < NP; k++) {
+      const int i = p0 + k * 64 + lane;
+      r[k] = 0;
+      if (i < p1) {
+        if (ce[k] - cb[k] <= kZSortMax) {
+          rlo = min(rlo, cb[k]);
+          rhi = max(rhi, ce[k]);
+        }
+      } else {
+        cb[k] = -1;
+        ce[k] = 0;
+      }
+    }
+#pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
-      for (int a = 0; a < 3; a++) {
-        mn[a] = fmin(mn[a], __shfl_xor(mn[a], off));
-        mx[a] = fmax(mx[a], __shfl_xor(mx[a], off));
+      rlo = min(rlo, __shfl_xor(rlo, off));
+      rhi = max(rhi, __shfl_xor(rhi, off));
+    }
+    // z ranks
+    for (int c0 = rlo; c0 < rhi; c0 += kSortStage) {
+      const int cnt = min(kSortStage, rhi - c0);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      {
+        // all of the stage's loads in flight at once (clamped positions)
+        double zt[kSortStage / 64];
+#pragma unroll
+        for (int u = 0; u < kSortStage / 64; u++)
+          zt[u] = grp[pb + c0 + min(lane + 64 * u, cnt - 1)].z;
+#pragma unroll
+        for (int u = 0; u < kSortStage / 64; u++)
+          if (lane + 64 * u < cnt) zz[lane + 64 * u] = zt[u];
+      }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+#pragma unroll
+      for (int k = 0; k < NP; k++) {
+        const int i = p0 + k * 64 + lane;
+        if (i < p1 && ce[k] - cb[k] <= kZSortMax) {
+          const int a = max(cb[k], c0) - c0, e = min(ce[k], c0 + cnt) - c0;
+          const int me = i - c0;
+          const double zi = v[k].z;
+          int rk = 0;
+          // earlier positions: z <= zi
+          const int e1 = min(e, me);
+          int t = a;
+          for (; t + 4 <= e1; t += 4) {
+            rk += (zz[t] <= zi ? 1 : 0) + (zz[t + 1] <= zi ? 1 : 0);
+            rk += (zz[t + 2] <= zi ? 1 : 0) + (zz[t + 3] <= zi ? 1 : 0);
+          }
+          for (; t < e1; t++) rk += zz[t] <= zi ? 1 : 0;
+          // later positions: z < zi
+          t = max(a, me + 1);
+          for (; t + 4 <= e; t += 4) {
+            rk += (zz[t] < zi ? 1 : 0) + (zz[t + 1] < zi ? 1 : 0);
+            rk += (zz[t + 2] < zi ? 1 : 0) + (zz[t + 3] < zi ? 1 : 0);
+          }
+          for (; t < e; t++) rk += zz[t] < zi ? 1 : 0;
+          r[k] += rk;
+        }
       }
     }
-    if (lane == 0) {
-      CellBox B;
-      for (int a = 0; a < 3; a++) {
-        B.lo[a] = mn[a];
-        B.hi[a] = mx[a];
+    // x, y extents: segmented min/max over the window's consecutive
+    // positions, carried from block to block (segment id: the cell start)
+    double cmn[2] = {DBL_MAX, DBL_MAX}, cmx[2] = {-DBL_MAX, -DBL_MAX};
+    int ccb = -2;   // cell of the carry
+#pragma unroll
+    for (int k = 0; k < NP; k++) {
+      const int i = p0 + k * 64 + lane;
+      const bool ok = i < p1;
+      double mn[2] = {ok ? v[k].x : DBL_MAX, ok ? v[k].y : DBL_MAX};
+      double mx[2] = {ok ? v[k].x : -DBL_MAX, ok ? v[k].y : -DBL_MAX};
+#pragma unroll
+      for (int off = 1; off < 64; off <<= 1) {
+        const int ocb = __shfl_up(cb[k], off);
+        fold_xy(mn, mx, off, lane >= off && ocb == cb[k]);
       }
-      cbox[G.cbase + c] = B;
+      if (ok && cb[k] == ccb) {
+        mn[0] = fmin(mn[0], cmn[0]);
+        mn[1] = fmin(mn[1], cmn[1]);
+        mx[0] = fmax(mx[0], cmx[0]);
+        mx[1] = fmax(mx[1], cmx[1]);
+      }
+      if (ok) {
+        const int n = ce[k] - cb[k];
+        const bool sorted = n <= kZSortMax;
+        const int rk = sorted ? r[k] : i - cb[k];
+        const int64_t d = pb + cb[k] + rk;
+        pos[d] = v[k];
+        const int cz = cell[k] % G.n[2], cxy = cell[k] / G.n[2];
+        strm[d] = stream_record(G, cxy / G.n[1], cxy % G.n[1], cz, v[k], mode);
+        CellBox *B = cbox + G.cbase + cell[k];
+        if (sorted) {
+          if (rk == 0) B->lo[2] = v[k].z;
+          if (rk == n - 1) B->hi[2] = v[k].z;
+          if (i == ce[k] - 1 && cb[k] >= p0) {
+            B->lo[0] = mn[0];
+            B->lo[1] = mn[1];
+            B->hi[0] = mx[0];
+            B->hi[1] = mx[1];
+          }
+        }
+      }
+      ccb = __shfl(cb[k], 63);
+      cmn[0] = __shfl(mn[0], 63);
+      cmn[1] = __shfl(mn[1], 63);
+      cmx[0] = __shfl(mx[0], 63);
+      cmx[1] = __shfl(mx[1], 63);
+    }
+    // the window's last cell, when it starts here and runs past the end:
+    // reduce its remaining positions (sorted cells only; larger ones below)
+    {
+      const int l = (p1 - p0 - 1) & 63, kl = (p1 - p0 - 1) >> 6;
+      int lcb = -1, lce = 0, lcell = 0;
+#pragma unroll
+      for (int k = 0; k < NP; k++) {
+        if (k == kl) {
+          lcb = __shfl(cb[k], l);
+          lce = __shfl(ce[k], l);
+          lcell = __shfl(cell[k], l);
+        }
+      }
+      if (lcb >= p0 && lce > p1 && lce - lcb <= kZSortMax) {
+        double mn[2] = {cmn[0], cmn[1]}, mx[2] = {cmx[0], cmx[1]};
+        for (int j0 = p1; j0 < lce; j0 += 256) {
+          double4 q[4];
+#pragma unroll
+          for (int u = 0; u < 4; u++) q[u] = grp[pb + min(j0 + 64 * u + lane, lce - 1)];
+#pragma unroll
+          for (int u = 0; u < 4; u++) {
+            mn[0] = fmin(mn[0], q[u].x);
+            mn[1] = fmin(mn[1], q[u].y);
+            mx[0] = fmax(mx[0], q[u].x);
+            mx[1] = fmax(mx[1], q[u].y);
+          }
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+          mn[0] = fmin(mn[0], __shfl_xor(mn[0], off));
+          mn[1] = fmin(mn[1], __shfl_xor(mn[1], off));
+          mx[0] = fmax(mx[0], __shfl_xor(mx[0], off));
+          mx[1] = fmax(mx[1], __shfl_xor(mx[1], off));
+        }
+        if (lane == 0) {
+          CellBox *B = cbox + G.cbase + lcell;
+          B->lo[0] = mn[0];
+          B->lo[1] = mn[1];
+          B->hi[0] = mx[0];
+          B->hi[1] = mx[1];
+        }
+      }
+    }
+    // cells above kZSortMax whose first position is in this window: the
+    // whole wave reduces their box
+#pragma unroll
+    for (int k = 0; k < NP; k++) {
+      const int i = p0 + k * 64 + lane;
+      uint64_t big = __ballot(i < p1 && ce[k] - cb[k] > kZSortMax && i == cb[k]);
+      while (big) {
+        const int l = __builtin_ctzll(big);
+        big &= big - 1;
+        const int b0 = __shfl(cb[k], l), e0 = __shfl(ce[k], l), c = __shfl(cell[k], l);
+        double mn[3] = {DBL_MAX, DBL_MAX, DBL_MAX}, mx[3] = {-DBL_MAX, -DBL_MAX, -DBL_MAX};
+        for (int j = b0 + lane; j < e0; j += 64) {
+          const double4 q = grp[pb + j];
+          mn[0] = fmin(mn[0], q.x); mx[0] = fmax(mx[0], q.x);
+          mn[1] = fmin(mn[1], q.y); mx[1] = fmax(mx[1], q.y);
+          mn[2] = fmin(mn[2], q.z); mx[2] = fmax(mx[2], q.z);
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+          for (int ax = 0; ax < 3; ax++) {
+            mn[ax] = fmin(mn[ax], __shfl_xor(mn[ax], off));
+            mx[ax] = fmax(mx[ax], __shfl_xor(mx[ax], off));
+          }
+        }
+        if (lane == 0) {
+          CellBox B;
+          for (int ax = 0; ax < 3; ax++) {
+            B.lo[ax] = mn[ax];
+            B.hi[ax] = mx[ax];
+          }
+          cbox[G.cbase + c] = B;
+        }
+      }
     }
   }
 }
@@ -377,9 +597,45 @@ __device__ inline int column_rank(int col, int nx, int ny) {
   return bx * B * ny + by * B * w + (cx - bx * B) * h + (cy - by * B);
 }
 
-// One wave per column: the column's cell starts are staged in the wave's LDS
-// slice, then one lane walks them.  Counts and offsets are indexed by the
-// column's queue position.
+// The same walk with the column's nz + 1 <= 64 cell starts held one per lane
+// (lane z holds cs[z]): the cell of a point and the cell where a tile ends
+// come from one ballot each, the span limit from one lane read, so a tile
+// costs a few instructions instead of a chain of dependent LDS reads.
+__device__ inline void walk_column_lanes(const GridGeom &G, int csv, int lane, int col,
+                                         int maxspan, int mock, int emit, Tile *out,
+                                         int64_t &ntile) {
+  const int nz = G.n[2];
+  int p = __builtin_amdgcn_readfirstlane(__builtin_amdgcn_readlane(csv, 0));
+  const int pend = __builtin_amdgcn_readlane(csv, nz);
+  int z = 0;
+  while (p < pend) {
+    // cell of point p: the first z' >= z with cs[z' + 1] > p
+    const uint64_t m0 = __ballot(lane > z && lane <= nz && csv > p);
+    z = (int)__builtin_ctzll(m0) - 1;
+    const int zmax = min(nz - 1, z + maxspan - 1);
+    const int q = min(p + kTileMax, __builtin_amdgcn_readlane(csv, zmax + 1));
+    // last cell of the tile: the first z' >= z with cs[z' + 1] >= q
+    const uint64_t m1 = __ballot(lane > z && lane <= nz && csv >= q);
+    const int z1 = (int)__builtin_ctzll(m1) - 1;
+    if (emit && lane == 0) {
+      Tile T;
+      T.p0 = G.pbase + p;
+      T.n = q - p;
+      T.mock = mock;
+      T.col = col;
+      T.cz0 = z;
+      T.cz1 = z1;
+      T.pad = 0;
+      out[ntile] = T;
+    }
+    ntile++;
+    p = q;
+  }
+}
+
+// One wave per column: the column's cell starts are held in lanes (columns of
+// up to 63 z-cells) or staged in the wave's LDS slice and walked by one lane.
+// Counts and offsets are indexed by the column's queue position.
 __global__ __launch_bounds__(256) void k_tiles(const GridGeom *geom, int nmock,
                                                const int *cstart, const int *maxspan,
                                                const int64_t *col_prefix, int *colcnt,
@@ -398,13 +654,21 @@ __global__ __launch_bounds__(256) void k_tiles(const GridGeom *geom, int nmock,
     const GridGeom &G = geom[lo];
     const int col = (int)(gcol - col_prefix[lo]);
     const int nz = G.n[2];
+    const int64_t q = col_prefix[lo] + column_rank(col, G.n[0], G.n[1]);
+    const int *src = cstart + G.sbase + (int64_t)col * nz;
+    if (nz < 64) {
+      const int csv = src[min(lane, nz)];
+      int64_t n = emit ? coloff[q] : 0;
+      walk_column_lanes(G, csv, lane, col, maxspan[lo], lo, emit, tiles, n);
+      if (!emit && lane == 0) colcnt[q] = (int)n;
+      continue;
+    }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
-    for (int z = lane; z <= nz; z += 64) cs[z] = cstart[G.sbase + col * nz + z];
+    for (int z = lane; z <= nz; z += 64) cs[z] = src[z];
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
     if (lane == 0) {
-      const int64_t q = col_prefix[lo] + column_rank(col, G.n[0], G.n[1]);
       int64_t n = emit ? coloff[q] : 0;
       walk_column(G, cs, col, maxspan[lo], lo, emit, tiles, n);
       if (!emit) colcnt[q] = (int)n;

@@ -375,6 +375,44 @@ def test_dense_cell_unsorted_path(native, prec):
     _check(g, refw, prec=prec)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_dense_cell_sorted_path(native, prec):
+    """Clusters of 700 and 2500 points, each inside one cell at refine 1 (below
+    the 4096-point z-sort limit): their z order takes several LDS stages of
+    the z-order pass and spans several position windows, some points share
+    their z exactly (ties broken by grouped position); counts, weighted sums
+    and the bounding-box tests agree with the oracle and with pruning off."""
+    rng = np.random.Generator(np.random.PCG64(43))
+    c1, c2 = np.array([212.5, 212.5, 212.5]), np.array([87.5, 312.5, 137.5])
+    a = c1 + rng.normal(scale=0.8, size=(2500, 3))
+    b = c2 + rng.normal(scale=0.5, size=(700, 3))
+    b[::7, 2] = b[0, 2]                       # exact z ties inside one cell
+    spread = rng.uniform(100.0, 330.0, (5000, 3))
+    p = np.concatenate([a, b, spread], 0) % 420.0
+    w = rng.uniform(0.5, 1.5, len(p))
+    cat = synth.Catalog(*(np.ascontiguousarray(p[:, k]) for k in range(3)), w=w)
+    edges = synth.log_edges(0.1, 25.0, 14)
+    _say("dense sorted cell", prec)
+    ref = oracle.xi(cat, edges, periodic=True, box=420.0)
+    d = native.to_device(cat)
+    for refine in [(1, 1, 1), (2, 2, 2)]:
+        g = native.countpairs_xi(d, edges, precision=prec, periodic=True, boxsize=420.0,
+                                 refine=refine, need_ravg=True)
+        _check(g, ref, weighted=True, prec=prec)
+        g = native.countpairs_xi(d, edges, precision=prec, periodic=True, boxsize=420.0,
+                                 refine=refine)
+        _check(g, ref, prec=prec)
+        h = native.countpairs_xi(d, edges, precision=prec, periodic=True, boxsize=420.0,
+                                 refine=refine, no_prune=True)
+        _check(h, ref, prec=prec)
+        assert g.stats["cell_pairs_pruned"] > 0
+    refw = oracle.wp(cat, edges, 40.0, 40, periodic=True, box=420.0)
+    for refine in [(1, 1, 1), (2, 2, 1)]:
+        g = native.countpairs_wp(d, edges, 40.0, 40, precision=prec, periodic=True,
+                                 boxsize=420.0, refine=refine)
+        _check(g, refw, prec=prec)
+
+
 def test_unique_mode_and_pruning_stats(native):
     cat = synth.clustered(30_000, 600, 1.5, 420.0, seed=6)
     edges = synth.log_edges(0.1, 25.0, 14)
