@@ -21,6 +21,7 @@ namespace cp {
 __global__ void k_bbox_partial(PointsDev a, PointsDev b, double *out, int *err);
 __global__ void k_bbox_final(const double *part, int nblk, double *out);
 __global__ void k_fill_i32(int *p, int64_t n, int v);
+__global__ void k_fill2_i32(int *a, int64_t na, int *b, int64_t nb);
 __global__ void k_fill_u64(unsigned long long *p, int64_t n);
 __global__ void k_fill_f64(double *p, int64_t n);
 __global__ void k_scan_sums(const int *in, const ScanSeg *segs, int nseg, int *tsum);
@@ -40,6 +41,8 @@ template <int MODE, int PREC, int W> __global__ void k_pairs(PairParams P);
 
 
 // ------------------------------------------------------------ error state
+
+constexpr int kMaxDevices = 64;   // devices whose per-device state the library keeps
 
 static thread_local std::string g_err;
 static thread_local cp_stats g_stats;
@@ -407,6 +410,28 @@ struct Arena {
 };
 static thread_local Arena g_arena;
 
+// Pinned host staging of the per-call upload and download, one buffer per
+// thread, grown on demand and kept until the process ends (each call has
+// synchronised its stream before it returns, so the next call may reuse it).
+struct Pinned {
+  char *p = nullptr;
+  size_t cap = 0;
+};
+static thread_local Pinned g_pin;
+
+static char *pinned_staging(size_t bytes) {
+  if (g_pin.cap < bytes) {
+    if (g_pin.p) (void)hipHostFree(g_pin.p);
+    g_pin = Pinned();
+    const size_t want = std::max<size_t>(bytes, (size_t)1 << 19);
+    void *q = nullptr;
+    if (hipHostMalloc(&q, want, hipHostMallocDefault) != hipSuccess) return nullptr;
+    g_pin.p = (char *)q;
+    g_pin.cap = want;
+  }
+  return g_pin.p;
+}
+
 struct Carver {
   char *p;
   size_t off = 0;
@@ -462,6 +487,12 @@ struct Smalls {
   int maxspan[2];
   int ntiles_dummy;
 };
+
+// Host staging sizes of one call: the small records and decision tables
+// (tables of at most kTabMax cells each, 256-byte aligned pieces), and the
+// histogram, weight sums, statistics and error flag.
+constexpr size_t kUpMax = sizeof(Smalls) + 2 * 8 * kTabMax + 16 * (kMaxBins + 1) + 8 * 256;
+constexpr size_t kDownMax = 3 * 8 * (size_t)kMaxBins * kMaxPiBins + 8 * kStatWords + 4 + 8 * 256;
 
 struct Call {
   int mode;          // XI / WP
@@ -535,16 +566,20 @@ static int launch_build(hipStream_t st, const PointsDev *d_pts, const GridGeom *
                         const SetBufs &S, int64_t n, int64_t ncell, int64_t ncol, int mode,
                         const ScanSeg *d_seg_cells, const ScanSeg *d_seg_cols,
                         const int64_t *d_win_prefix, const int64_t *d_col_prefix,
-                        const int *d_maxspan, int *d_err, bool tiles) {
-  const int fb = (int)std::min<int64_t>(std::max<int64_t>((ncell * kCountStride + 255) / 256, 1), 4096);
+                        const int *d_maxspan, int *d_err, bool tiles, int *zero = nullptr,
+                        int64_t zero_words = 0) {
+  // the cell counters (and the caller's extra range) cleared by one launch
+  const int64_t nfill = ncell * kCountStride;
+  const int fb = (int)std::min<int64_t>(std::max<int64_t>((nfill + zero_words + 255) / 256, 1), 4096);
   (void)hipGetLastError();
-  hipLaunchKernelGGL(k_fill_i32, dim3(fb), dim3(256), 0, st, S.ccount, ncell * kCountStride, 0);
+  hipLaunchKernelGGL(k_fill2_i32, dim3(fb), dim3(256), 0, st, S.ccount, nfill, zero, zero_words);
   const int ab = (int)std::min<int64_t>(std::max<int64_t>((n + 255) / 256, 1), 8192);
   if (n > 0)
     hipLaunchKernelGGL(k_assign, dim3(ab, 1), dim3(256), 0, st, d_pts, d_geom, S.ccount, S.cid,
                        S.rank, d_err);
   const unsigned sc = (unsigned)scan_tiles(ncell);
-  hipLaunchKernelGGL(k_scan_sums, dim3(sc), dim3(256), 0, st, S.ccount, d_seg_cells, 1, S.tsum);
+  if (sc > 1)   // a single tile needs no tile totals
+    hipLaunchKernelGGL(k_scan_sums, dim3(sc), dim3(256), 0, st, S.ccount, d_seg_cells, 1, S.tsum);
   hipLaunchKernelGGL(k_scan_apply, dim3(sc), dim3(256), 0, st, S.ccount, S.cstart, d_seg_cells, 1,
                      S.tsum);
   if (n > 0)
@@ -560,7 +595,8 @@ static int launch_build(hipStream_t st, const PointsDev *d_pts, const GridGeom *
     hipLaunchKernelGGL(k_tiles, dim3(tb), dim3(256), 0, st, d_geom, 1, S.cstart, d_maxspan,
                        d_col_prefix, S.colcnt, S.coloff, S.tiles, 0);
     const unsigned tc = (unsigned)scan_tiles(ncol);
-    hipLaunchKernelGGL(k_scan_sums, dim3(tc), dim3(256), 0, st, S.colcnt, d_seg_cols, 1, S.tsum);
+    if (tc > 1)
+      hipLaunchKernelGGL(k_scan_sums, dim3(tc), dim3(256), 0, st, S.colcnt, d_seg_cols, 1, S.tsum);
     hipLaunchKernelGGL(k_scan_apply, dim3(tc), dim3(256), 0, st, S.colcnt, S.coloff, d_seg_cols,
                        1, S.tsum);
     hipLaunchKernelGGL(k_tiles, dim3(tb), dim3(256), 0, st, d_geom, 1, S.cstart, d_maxspan,
@@ -710,6 +746,48 @@ static int make_binning(int mode, int prec, const double *edges, int nedges, dou
   return CP_OK;
 }
 
+// The binning of the last call on this thread, reused while its inputs are
+// unchanged (the tables cost ~10 us to build; repeated calls on one
+// configuration are the common case).  run() takes the reference after any
+// tuning runs, so no nested call replaces it while it is in use.
+struct BinningKey {
+  int mode = -1, prec = -1, nedges = 0, npi = 0;
+  double pimax = 0, M = 0, cs[3] = {0, 0, 0};
+  Fixed<double, kMaxBins + 1> edges;
+  bool operator==(const BinningKey &k) const {
+    if (mode != k.mode || prec != k.prec || nedges != k.nedges || npi != k.npi ||
+        pimax != k.pimax || M != k.M || cs[0] != k.cs[0] || cs[1] != k.cs[1] || cs[2] != k.cs[2])
+      return false;
+    for (int i = 0; i < nedges; i++)
+      if (edges[i] != k.edges[i]) return false;
+    return true;
+  }
+};
+static thread_local BinningKey g_bin_key;
+static thread_local Binning g_bin;
+
+static int cached_binning(int mode, int prec, const double *edges, int nedges, double pimax,
+                          int npi, const Geometry &g, double M, const Binning *&out) {
+  BinningKey k;
+  k.mode = mode;
+  k.prec = prec;
+  k.nedges = nedges;
+  k.npi = npi;
+  k.pimax = pimax;
+  k.M = M;
+  for (int a = 0; a < 3; a++) k.cs[a] = g.cs[a];
+  k.edges.assign(nedges, 0.0);
+  for (int i = 0; i < nedges; i++) k.edges[i] = edges[i];
+  if (!(k == g_bin_key)) {
+    g_bin_key = BinningKey();   // invalid until the tables are built
+    const int rc = make_binning(mode, prec, edges, nedges, pimax, npi, g, M, g_bin);
+    if (rc) return rc;
+    g_bin_key = k;
+  }
+  out = &g_bin;
+  return CP_OK;
+}
+
 static int map_err_flags(int flags) {
   if (flags & 1) return fail(CP_ERR_NONFINITE, "non-finite coordinate or weight");
   if (flags & 2) return fail(CP_ERR_OUT_OF_BOX, "periodic coordinate outside [0, boxsize)");
@@ -853,16 +931,17 @@ static int run(const Call &c, uint64_t *npairs, double *wsum, double *ravg) {
   const double rmax = c.edges[nb];
 
   const bool noalloc = c.scratch != nullptr;
-  hipEvent_t ev[4] = {};
-  struct EvGuard {
-    hipEvent_t *e;
-    ~EvGuard() {
-      for (int i = 0; i < 4; i++)
-        if (e[i]) (void)hipEventDestroy(e[i]);
-    }
-  } evg{ev};
+  // timing events: created once per thread and device, reused by every call
+  // (the call without allocation creates and records none)
+  static thread_local hipEvent_t tl_ev[kMaxDevices][4];
+  hipEvent_t *ev = nullptr;
   if (!noalloc) {
-    for (auto &e : ev) HIPCHK(hipEventCreate(&e));
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(CP_ERR_DEVICE, "device index out of range");
+    ev = tl_ev[dev];
+    for (int i = 0; i < 4; i++)
+      if (!ev[i]) HIPCHK(hipEventCreate(&ev[i]));
     HIPCHK(hipEventRecord(ev[0], st));
   }
 
@@ -974,8 +1053,9 @@ static int run(const Call &c, uint64_t *npairs, double *wsum, double *ravg) {
   double M = 0;
   for (int a = 0; a < 3; a++) M = std::max(M, std::fabs(g.lo[a]) + g.ext[a]);
   if (o.periodic) M = std::max(M, o.boxsize);
-  Binning B;
-  if ((rc = make_binning(c.mode, prec, c.edges, c.nedges, c.pimax, npi, g, M, B))) return rc;
+  const Binning *Bp = nullptr;
+  if ((rc = cached_binning(c.mode, prec, c.edges, c.nedges, c.pimax, npi, g, M, Bp))) return rc;
+  const Binning &B = *Bp;
 
   const int64_t ncell = (int64_t)g.n[0] * g.n[1] * g.n[2];
   const int64_t ncol = (int64_t)g.n[0] * g.n[1];
@@ -1066,10 +1146,12 @@ static int run(const Call &c, uint64_t *npairs, double *wsum, double *ravg) {
     // the small records and tables are carved consecutively: one upload
     char *up0 = (char *)d_sm;
     const size_t upn = (size_t)((char *)(d_a32 + c.nedges) - up0);
-    // tables of at most kTabMax cells each, 256-byte aligned pieces
-    constexpr size_t kUpMax = sizeof(Smalls) + 2 * 8 * kTabMax + 16 * (kMaxBins + 1) + 8 * 256;
     if (upn > kUpMax) return fail(CP_ERR_INTERNAL, "upload block larger than expected");
-    alignas(16) char hup[kUpMax];
+    // staging: pinned (the copy is a plain DMA); on the stack for the call
+    // without allocation, or if pinned memory cannot be had
+    alignas(16) char hstack[kUpMax];
+    char *hup = noalloc ? nullptr : pinned_staging(kUpMax + kDownMax);
+    if (!hup) hup = hstack;
     memset(hup, 0, upn);
     auto put = [&](const void *dev, const void *src, size_t bytes) {
       if (bytes) memcpy(hup + ((const char *)dev - up0), src, bytes);
@@ -1082,18 +1164,14 @@ static int run(const Call &c, uint64_t *npairs, double *wsum, double *ravg) {
     put(d_a32, B.A32.data(), (size_t)c.nedges * 4);
     HIPCHK(hipMemcpyAsync(up0, hup, upn, hipMemcpyHostToDevice, st));
   }
-  {
-    // histogram, weight sums, statistics and error flag are carved
-    // consecutively: one fill clears them all (zero bits are 0 and 0.0)
-    const int64_t words = (int64_t)(((char *)(d_err + 1) - (char *)d_hist) / 4);
-    hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)std::min<int64_t>((words + 255) / 256, 64)),
-                       dim3(256), 0, st, (int *)d_hist, words, 0);
-  }
-
   // ---- cell build
+  // histogram, weight sums, statistics and error flag are carved
+  // consecutively: the build's first fill clears them too (zero bits are 0
+  // and 0.0)
+  const int64_t words = (int64_t)(((char *)(d_err + 1) - (char *)d_hist) / 4);
   rc = launch_build(st, &d_sm->pts[0], &d_sm->geom[0], S1, p1.n, ncell, ncol, c.mode,
                     &d_sm->seg[0], &d_sm->seg[1], d_sm->win_prefix[0], d_sm->col_prefix,
-                    d_sm->maxspan, d_err, true);
+                    d_sm->maxspan, d_err, true, (int *)d_hist, words);
   if (rc) return rc;
   if (!autoc) {
     rc = launch_build(st, &d_sm->pts[1], &d_sm->geom[1], S2, p2.n, ncell, ncol, c.mode,
@@ -1181,12 +1259,20 @@ static int run(const Call &c, uint64_t *npairs, double *wsum, double *ravg) {
     hwrv.resize(nout);
     char *dn0 = (char *)d_hist;
     const size_t dnn = (size_t)((char *)(d_err + 1) - dn0);
-    std::vector<char> hdn(dnn);
-    HIPCHK(hipMemcpyAsync(hdn.data(), dn0, dnn, hipMemcpyDeviceToHost, st));
+    if (dnn > kDownMax) return fail(CP_ERR_INTERNAL, "download block larger than expected");
+    std::vector<char> hvec;
+    char *hdn = pinned_staging(kUpMax + kDownMax);
+    if (hdn) {
+      hdn += kUpMax;
+    } else {
+      hvec.resize(dnn);
+      hdn = hvec.data();
+    }
+    HIPCHK(hipMemcpyAsync(hdn, dn0, dnn, hipMemcpyDeviceToHost, st));
     HIPCHK(hipEventRecord(ev[3], st));
     HIPCHK(hipStreamSynchronize(st));
     auto get = [&](void *dst, const void *dev, size_t bytes) {
-      memcpy(dst, hdn.data() + ((const char *)dev - dn0), bytes);
+      memcpy(dst, hdn + ((const char *)dev - dn0), bytes);
     };
     get(h.data(), d_hist, 8 * (size_t)nout);
     if (weighted) {
@@ -1261,7 +1347,6 @@ static int run(const Call &c, uint64_t *npairs, double *wsum, double *ravg) {
 constexpr size_t kScratchBytes = (size_t)64 << 20;
 static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
-constexpr int kMaxDevices = 64;
 static std::mutex g_scratch_mu;
 static void *g_scratch_ptr[kMaxDevices];
 

@@ -83,6 +83,15 @@ __global__ void k_fill_i32(int *p, int64_t n, int v) {
     p[i] = v;
 }
 
+// Zero two ranges in one launch.
+__global__ void k_fill2_i32(int *a, int64_t na, int *b, int64_t nb) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < na + nb;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    if (i < na) a[i] = 0;
+    else b[i - na] = 0;
+  }
+}
+
 __global__ void k_fill_u64(unsigned long long *p, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)

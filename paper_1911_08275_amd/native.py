@@ -149,6 +149,15 @@ class DevicePoints:
         return int(self.x.shape[0])
 
     def struct(self) -> cp_points:
+        """The C-ABI view of the point set, validated once per set of tensors
+        (re-validated whenever a tensor, its storage or its length changes)."""
+        key = (self.x.data_ptr(), self.y.data_ptr(), self.z.data_ptr(),
+               None if self.w is None else self.w.data_ptr(),
+               self.x.shape, self.y.shape, self.z.shape,
+               None if self.w is None else self.w.shape, self.x.dtype)
+        c = self.__dict__.get("_struct")
+        if c is not None and c[0] == key:
+            return c[1]
         import torch
         dt = self.x.dtype
         if dt == torch.float64:
@@ -166,8 +175,12 @@ class DevicePoints:
         if self.w is not None:
             if self.w.dtype != torch.float64 or not self.w.is_cuda or not self.w.is_contiguous():
                 raise ValueError("w must be a contiguous float64 GPU tensor")
+            if self.w.dim() != 1 or self.w.shape[0] != self.x.shape[0]:
+                raise ValueError("w must be 1-D with one weight per point")
             w = self.w.data_ptr()
-        return cp_points(self.n, self.x.data_ptr(), self.y.data_ptr(), self.z.data_ptr(), w, code)
+        st = cp_points(self.n, self.x.data_ptr(), self.y.data_ptr(), self.z.data_ptr(), w, code)
+        self.__dict__["_struct"] = (key, st)
+        return st
 
 
 def to_device(cat, device="cuda", weights: bool = True) -> DevicePoints:
@@ -180,34 +193,49 @@ def to_device(cat, device="cuda", weights: bool = True) -> DevicePoints:
     return DevicePoints(t[0], t[1], t[2], w)
 
 
+_DEFAULT_OPTIONS = None
+_PREC = None
+_MODES = None
+
+
+def _current_stream() -> int:
+    """torch's current HIP stream of the current device (0: the null stream)."""
+    import torch
+    try:
+        return int(torch._C._cuda_getCurrentRawStream(torch.cuda.current_device()))
+    except Exception:
+        try:
+            return int(torch.cuda.current_stream().cuda_stream)
+        except Exception:
+            return 0
+
+
 def options(precision: str = "fp32", periodic: bool = False, boxsize: float = 0.0,
             refine: Optional[Sequence[int]] = None, need_ravg: bool = False,
             count_mode: str = "ordered", stream=None, workspace=None,
             no_prune: bool = False) -> cp_options:
-    o = cp_options()
-    lib().cp_default_options(ctypes.byref(o))
-    o.precision = {"fp32": CP_PREC_FP32_RECHECK, "fp64": CP_PREC_FP64}[precision]
+    global _DEFAULT_OPTIONS, _PREC, _MODES
+    if _DEFAULT_OPTIONS is None:
+        d = cp_options()
+        lib().cp_default_options(ctypes.byref(d))
+        _DEFAULT_OPTIONS = bytes(d)
+        _PREC = {"fp32": CP_PREC_FP32_RECHECK, "fp64": CP_PREC_FP64}
+        _MODES = {"ordered": CP_ORDERED, "unique": CP_UNIQUE}
+    o = cp_options.from_buffer_copy(_DEFAULT_OPTIONS)
+    o.precision = _PREC[precision]
     o.periodic = 1 if periodic else 0
     o.boxsize = float(boxsize)
     if refine is not None and refine != "auto":
         # None or "auto": refine 0, the library tunes the launch settings
-        for a in range(3):
-            o.refine[a] = int(refine[a])
+        o.refine[0], o.refine[1], o.refine[2] = int(refine[0]), int(refine[1]), int(refine[2])
     o.need_ravg = 1 if need_ravg else 0
-    o.count_mode = {"ordered": CP_ORDERED, "unique": CP_UNIQUE}[count_mode]
+    o.count_mode = _MODES[count_mode]
     o.no_prune = 1 if no_prune else 0
     if workspace is not None:
         # a caller-owned device buffer (e.g. a torch uint8 tensor)
-        o.workspace = ctypes.c_void_p(workspace.data_ptr())
+        o.workspace = workspace.data_ptr()
         o.workspace_bytes = workspace.numel() * workspace.element_size()
-    if stream is not None:
-        o.stream = ctypes.c_void_p(int(getattr(stream, "cuda_stream", stream)))
-    else:
-        try:
-            import torch
-            o.stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
-        except Exception:
-            o.stream = None
+    o.stream = int(getattr(stream, "cuda_stream", stream)) if stream is not None else _current_stream()
     return o
 
 
