@@ -620,6 +620,26 @@ static int num_cus() {
 // Waves per pair-kernel workgroup: four, or fewer when the per-wave
 // histograms (w_p with many bins, weighted) would not fit the 160 KB of LDS;
 // 0 when not even one wave's fits.
+// Copies of the w_p wave histogram: the tile's points are z-neighbours of
+// one column, so for one streamed point most lanes add to the same few
+// (r_p, pi) counters and their LDS atomics serialise; lane l adds to copy
+// l mod wpc, the copies of a counter in adjacent words.  The most copies
+// (up to 8) that still leave room for five 4-wave workgroups per CU (the
+// pair kernel's register-bound occupancy); CP_WP_COPIES (1, 2, 4 or 8)
+// overrides the choice.
+static int wp_copies(int mode, int prec, int weighted, int n32, int n64, int nb, int npi) {
+  if (mode != WP) return 1;
+  if (const char *e = getenv("CP_WP_COPIES")) {
+    const int c = atoi(e);
+    if (c == 1 || c == 2 || c == 4 || c == 8) return c;
+  }
+  for (int c = 8; c > 1; c >>= 1) {
+    const LdsLayout L = lds_layout(mode, prec, weighted, n32, n64, nb, npi, c);
+    if (L.common + 4 * L.wave_bytes + kStaticLds <= (size_t)160 * 1024 / 5) return c;
+  }
+  return 1;
+}
+
 static int pick_waves(const LdsLayout &LY, size_t *lds, int most = 4) {
   for (int nw = std::min(4, std::max(1, most)); nw >= 1; nw--) {
     const size_t l = LY.common + (size_t)nw * LY.wave_bytes;
@@ -1228,7 +1248,8 @@ static int run(const Call &c, uint64_t *npairs, double *wsum, double *ravg) {
   P.hwr = d_hwr;
   P.stats = d_stats;
   P.hist_stride = nout;
-  const LdsLayout LY = lds_layout(c.mode, prec, weighted, n32, n64, nb, npi);
+  P.wpc = wp_copies(c.mode, prec, weighted, n32, n64, nb, npi);
+  const LdsLayout LY = lds_layout(c.mode, prec, weighted, n32, n64, nb, npi, P.wpc);
   size_t lds = 0;
   const int nwaves = pick_waves(LY, &lds, waves_most);
   if (!nwaves) return fail(CP_ERR_INVALID_ARG, "too many bins for the LDS budget");
@@ -1526,6 +1547,7 @@ struct Batch {
   size_t lds = 0;
   int nwaves = 4;
   int waves_most = 4;      // launch settings from the caller or the tuner
+  int wpc = 1;             // copies of the w_p wave histogram
   int chunk_pct = 100;
   double pimax = 0.0;
   PairParams P{};
@@ -1590,8 +1612,9 @@ static int batch_prepare(cp_plan &pl, Batch &b, int mode, int prec, const double
   b.ncol_tot = b.ncol * pl.nmock;
   b.segs.push_back({0, 0, b.ncol_tot, 0, 1});
   b.maxtiles = max_tiles_bound(b.npts_tot, b.ncell_tot, b.ncol_tot);
+  b.wpc = wp_copies(mode, b.prec, 0, (int)b.B.t32.e.size(), (int)b.B.t64.e.size(), b.nb, b.npi);
   const LdsLayout LY = lds_layout(mode, b.prec, 0, (int)b.B.t32.e.size(),
-                                       (int)b.B.t64.e.size(), b.nb, b.npi);
+                                  (int)b.B.t64.e.size(), b.nb, b.npi, b.wpc);
   b.nwaves = pick_waves(LY, &b.lds, b.waves_most);
   if (!b.nwaves) return fail(CP_ERR_INVALID_ARG, "too many bins for the LDS budget");
   return CP_OK;
@@ -1680,6 +1703,7 @@ static int batch_upload(cp_plan &pl, Batch &b) {
   P.dpi = b.B.dpi;
   P.inv_dpi = 1.0 / b.B.dpi;
   P.npi = b.npi;
+  P.wpc = b.wpc;
   P.inv_dpi32 = b.B.inv_dpi32;
   P.pi_delta = b.B.pi_delta;
   P.pi_lo32 = b.B.pi_lo32;

@@ -151,6 +151,7 @@ struct PairParams {
   // wp
   double pimax, dpi, inv_dpi;   // inv_dpi = fl(1 / dpi)
   int npi;
+  int wpc;                   // copies of the wave's histogram (power of two)
   float inv_dpi32, pi_delta, pi_lo32, pi_hi32;
   // flags
   int autocorr;
@@ -204,8 +205,10 @@ __host__ __device__ constexpr bool xi_f32_weighted(int mode, int prec, int weigh
 // group of four records adds at most 4 x 64.
 constexpr int kListCap = 64 + 4 * 64;
 
+// wpc: copies of the w_p histogram (and weight sums) per wave, interleaved
+// counter by counter; lane l adds to copy l mod wpc.
 __host__ __device__ inline LdsLayout lds_layout(int mode, int prec, int weighted, int n32, int n64,
-                                               int nb, int npi) {
+                                               int nb, int npi, int wpc = 1) {
   LdsLayout L;
   size_t off = 0;
   L.tab32 = off;
@@ -217,7 +220,7 @@ __host__ __device__ inline LdsLayout lds_layout(int mode, int prec, int weighted
   off += (size_t)(nb + 1) * 8;
   L.common = align16(off);
   const int NS = nb + 2;
-  const size_t words = mode == XI ? (size_t)NS * 64 : (size_t)NS * npi;
+  const size_t words = mode == XI ? (size_t)NS * 64 : (size_t)NS * npi * wpc;
   L.wave_hist = align16(words * 4);
   // weight sums are shared by the wave (one row of slots), not lane-private
   L.wave_w = weighted ? (mode == XI ? (size_t)NS * kWStripe : words) * 8 : 0;

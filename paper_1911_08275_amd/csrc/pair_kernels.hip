@@ -200,19 +200,24 @@ __device__ inline void flush_hist(const PairParams &P, WaveArea A, int mock, int
       for (int t = lane; t < 2 * NS * kWStripe; t += 64) A.hw[t] = 0.0;
     }
   } else {
-    const int npi = P.npi;
+    const int npi = P.npi, wpc = P.wpc;
     for (int t = lane; t < nb * npi; t += 64) {
-      uint32_t v = A.hist[npi + t];
+      uint32_t v = 0;
+      for (int c = 0; c < wpc; c++) v += A.hist[(npi + t) * wpc + c];
       if (v) atomicAdd(gh + t, (unsigned long long)v);
       if (W) {
-        double a = A.hw[2 * (npi + t)], b = A.hw[2 * (npi + t) + 1];
+        double a = 0.0, b = 0.0;
+        for (int c = 0; c < wpc; c++) {
+          a += A.hw[2 * ((npi + t) * wpc + c)];
+          b += A.hw[2 * ((npi + t) * wpc + c) + 1];
+        }
         if (a != 0.0) unsafeAtomicAdd(P.hw + (int64_t)mock * P.hist_stride + t, a);
         if (b != 0.0) unsafeAtomicAdd(P.hwr + (int64_t)mock * P.hist_stride + t, b);
       }
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
-    for (int t = lane; t < NS * npi; t += 64) {
+    for (int t = lane; t < NS * npi * wpc; t += 64) {
       A.hist[t] = 0u;
       if (W) {
         A.hw[2 * t] = 0.0;
@@ -580,7 +585,7 @@ __device__ inline WpHit wp_decide(const PairParams &P, const uint2 *tab32, const
 // Binary64 re-evaluation of one uncertain wp pair (unweighted).
 template <bool SHIFT>
 __device__ inline void recheck_wp(const PairParams &P, WaveArea A, const LanePt &L, const Unit &U,
-                                  int j, const double *sE) {
+                                  int j, const double *sE, int cpy) {
   sdouble *DP = (sdouble *)U.pos;
   const double ux = DP[4 * j], uy = DP[4 * j + 1], uz = DP[4 * j + 2];
   const int wrapax[3] = {0, 0, 0};
@@ -589,27 +594,45 @@ __device__ inline void recheck_wp(const PairParams &P, WaveArea A, const LanePt 
   const double rp2 = dx * dx + dy * dy;
   const double pz64 = fabs(dz);
   if (pz64 < P.pimax && rp2 < P.EB)
-    atomicAdd(&A.hist[exact_slot(sE, P.nb, rp2) * P.npi + exact_pibin(pz64, P.dpi, P.inv_dpi, P.npi)], 1u);
+    atomicAdd(&A.hist[(exact_slot(sE, P.nb, rp2) * P.npi +
+                       exact_pibin(pz64, P.dpi, P.inv_dpi, P.npi)) * P.wpc + cpy], 1u);
 }
 
 // wp, unweighted: certain pairs are counted at once, uncertain ones
-// re-evaluated in binary64 on the spot (as in the general xi loop).
+// re-evaluated in binary64 on the spot (as in the general xi loop).  The same
+// decisions as wp_decide, with the binary32 r_p^2 and |dz| formed once and
+// the table index clamped below only (v < AB32 keeps it inside the table).
 template <bool OWN, bool SHIFT>
 __device__ inline void loop_wp_f32(const PairParams &P, WaveArea A, const LanePt &L, int lane,
                                    float rx, float ry, float rz, float ra, const Unit &U,
                                    const uint2 *tab32, const double *sE, uint32_t &nrechk) {
-  const int npi = P.npi;
+  const int npi = P.npi, wpc = P.wpc, lo = P.tab32_lo, sh = P.tab_shift;
+  const int row = npi * wpc;                       // histogram words per slot
+  const int base = lane & (wpc - 1);
+  const uint2 *tb = tab32 - lo;
+  const float AB = P.AB32, phi = P.pi_hi32, plo = P.pi_lo32, inv = P.inv_dpi32;
+  const float pd = P.pi_delta, pd1 = 1.0f - P.pi_delta;
   uint32_t nunc = 0;
   stream_f32(U.strm, U.jb, U.je, [&](int j, float qx, float qy, float qz, float qw) {
-    const float s0 = __builtin_fmaf(ry, qy, __builtin_fmaf(rx, qx, ra)) + qw;
-    bool pre = (s0 < P.AB32) && (fabsf(qz - rz) < P.pi_hi32);
+    const float v = __builtin_fmaf(ry, qy, __builtin_fmaf(rx, qx, ra)) + qw;
+    const float pz = fabsf(qz - rz);
+    bool pre = (v < AB) && (pz < phi);
     if (OWN) pre = pre && (j > L.iloc);
     if (pre) {
-      const WpHit h = wp_decide<OWN>(P, tab32, L, rx, ry, rz, ra, j, qx, qy, qz, qw);
-      if (h.inr && !h.unc) atomicAdd(&A.hist[h.slot * npi + h.l], 1u);
-      else if (h.unc) {
-        recheck_wp<SHIFT>(P, A, L, U, j, sE);
+      const uint2 e = tb[max(__float_as_int(v) >> sh, lo)];
+      const float f = pz * inv;
+      const float fl = floorf(f);
+      const float fr = f - fl;
+      const bool ch = v >= __uint_as_float(e.y);
+      const bool unc = (v >= __uint_as_float(e.x) && !ch) || fr < pd || fr > pd1 || pz >= plo;
+      if (unc) {
+        recheck_wp<SHIFT>(P, A, L, U, j, sE, base);
         nunc++;
+      } else {
+        const int slot = (int)(e.y & 63u) - 1 + (ch ? 1 : 0);
+        const int l = min((int)fl, npi - 1);
+        // 24-bit products (full rate; the 32-bit multiply is quarter rate)
+        atomicAdd(&A.hist[__umul24(slot, row) + __umul24(l, wpc) + base], 1u);
       }
     }
   });
@@ -621,7 +644,7 @@ template <bool OWN, bool SHIFT>
 __device__ inline void loop_wp_f32_w(const PairParams &P, WaveArea A, const LanePt &L, int lane,
                                      float rx, float ry, float rz, float ra, const Unit &U,
                                      const uint2 *tab32, const double *sE, uint32_t &nrechk) {
-  const int nb = P.nb, npi = P.npi;
+  const int nb = P.nb, npi = P.npi, wpc = P.wpc, cpy = lane & (wpc - 1);
   const int wrapax[3] = {0, 0, 0};
   stream_w(U.strm, U.pos, U.jb, U.je,
            [&](int j, float qx, float qy, float qz, float qw, double ux, double uy, double uz,
@@ -643,8 +666,9 @@ __device__ inline void loop_wp_f32_w(const PairParams &P, WaveArea A, const Lane
                }
                if (keep) {
                  const double ww = L.w * uw;
-                 atomicAdd(&A.hist[sl * npi + ll], 1u);
-                 add_w(A.hw + 2 * (sl * npi + ll), ww, ww * sep_sqrt(__builtin_fma(dx, dx, dy * dy)));
+                 const int c = (sl * npi + ll) * wpc + cpy;
+                 atomicAdd(&A.hist[c], 1u);
+                 add_w(A.hw + 2 * c, ww, ww * sep_sqrt(__builtin_fma(dx, dx, dy * dy)));
                }
              }
            });
@@ -976,10 +1000,11 @@ __device__ inline void loop_f64(const PairParams &P, WaveArea A, const LanePt &L
       if (inr) {
         const int slot = slot64(tab64, lo, hi, sh, sE, nb, rp2);
         const int l = exact_pibin(pz64, P.dpi, P.inv_dpi, npi);
-        atomicAdd(&A.hist[slot * npi + l], 1u);
+        const int c = (slot * npi + l) * P.wpc + (lane & (P.wpc - 1));
+        atomicAdd(&A.hist[c], 1u);
         if (W) {
           const double ww = L.w * uw;
-          add_w(A.hw + 2 * (slot * npi + l), ww, ww * sep_sqrt(rp2));
+          add_w(A.hw + 2 * c, ww, ww * sep_sqrt(rp2));
         }
       }
     }
@@ -1010,7 +1035,7 @@ void k_pairs(PairParams P) {
   const int wid = threadIdx.x >> 6;
   const int n32 = (PREC == F32R && !xi_f32_weighted(MODE, PREC, W)) ? P.tab32_hi - P.tab32_lo + 1 : 0;
   const int n64 = P.tab64_hi - P.tab64_lo + 1;
-  const LdsLayout LY = lds_layout(MODE, PREC, W, n32, n64, P.nb, P.npi);
+  const LdsLayout LY = lds_layout(MODE, PREC, W, n32, n64, P.nb, P.npi, P.wpc);
   uint2 *tab32 = (uint2 *)(smem + LY.tab32);
   uint2 *tab64 = (uint2 *)(smem + LY.tab64);
   double *sE = (double *)(smem + LY.E);
@@ -1023,7 +1048,7 @@ void k_pairs(PairParams P) {
   A.hw = (double *)(wb + LY.wave_hist);
   A.list = (uint32_t *)(wb + LY.wave_list);
   const int NS = P.nslots;
-  const int hwords = MODE == XI ? NS * 64 : NS * P.npi;
+  const int hwords = MODE == XI ? NS * 64 : NS * P.npi * P.wpc;
   const int wwords = MODE == XI ? NS * kWStripe : hwords;
   for (int t = lane; t < hwords; t += 64) A.hist[t] = 0u;
   if (W) {
