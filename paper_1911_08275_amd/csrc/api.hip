@@ -627,14 +627,15 @@ static int num_cus() {
 // (up to 8) that still leave room for five 4-wave workgroups per CU (the
 // pair kernel's register-bound occupancy); CP_WP_COPIES (1, 2, 4 or 8)
 // overrides the choice.
-static int wp_copies(int mode, int prec, int weighted, int n32, int n64, int nb, int npi) {
-  if (mode != WP) return 1;
+static int wp_copies(int mode, int prec, int weighted, int n32, int n64, int nb, int npi,
+                     int nx = 0, int nbx = 0) {
+  if (mode != WP && mode != WPXI) return 1;
   if (const char *e = getenv("CP_WP_COPIES")) {
     const int c = atoi(e);
     if (c == 1 || c == 2 || c == 4 || c == 8) return c;
   }
   for (int c = 8; c > 1; c >>= 1) {
-    const LdsLayout L = lds_layout(mode, prec, weighted, n32, n64, nb, npi, c);
+    const LdsLayout L = lds_layout(mode, prec, weighted, n32, n64, nb, npi, c, nx, nbx);
     if (L.common + 4 * L.wave_bytes + kStaticLds <= (size_t)160 * 1024 / 5) return c;
   }
   return 1;
@@ -687,6 +688,10 @@ static int launch_pairs_t(hipStream_t st, const PairParams &P, size_t lds, int n
 
 static int launch_pairs(hipStream_t st, int mode, int prec, int w, const PairParams &P,
                         size_t lds, int nwaves) {
+  if (mode == WPXI) {
+    if (prec != F32R || w) return fail(CP_ERR_INTERNAL, "fused w_p + xi is binary32, unweighted");
+    return launch_pairs_t<WPXI, F32R, 0>(st, P, lds, nwaves);
+  }
   if (mode == XI) {
     if (prec == F32R)
       return w ? launch_pairs_t<XI, F32R, 1>(st, P, lds, nwaves)
@@ -764,6 +769,55 @@ static int make_binning(int mode, int prec, const double *edges, int nedges, dou
     B.pi_lo32 = B.pi_hi32 = 0.f;
   }
   return CP_OK;
+}
+
+// Binning of xi inside a fused w_p + xi launch.  The kernel forms the xi
+// estimate s~ = fl32(pi~ * pi~ + v~) from the w_p estimates: v~ of r_p^2
+// (error at most eps of the w_p bound) and pi~ of |dz| (error at most
+// eta_pi).  Against the binary64 reference s = fl(fl(dx^2 + dy^2) + fl(dz^2)):
+//   |s~ - s| <= u32 (pi~^2 + v~) + (pi~ + |dz|) eta_pi + eps + 2 u64 s.
+// A decision is only taken for s~ < AB32x = up(E_B + bound), where pi~ and
+// |dz| are at most Z = sqrt(E_B + bound + eps) + eta_pi; the bound and Z are
+// iterated to a fixed point, and twice the bound makes the bands.  Returns
+// false (no fusion) when the bound is not small against E_B.
+static bool make_binning_wpxi(const double *edges, int nedges, const Binning &Bw, Binning &Bx) {
+  const int nb = nedges - 1;
+  Bx.E.resize(nedges);
+  for (int k = 0; k < nedges; k++) Bx.E[k] = edges[k] * edges[k];
+  const double EB = Bx.E[nb];
+  const double u = std::ldexp(1.0, -24), u64 = std::ldexp(1.0, -53);
+  const double eta = Bw.bnd.eta_pi, epsw = Bw.bnd.eps;
+  double bound = 0.0;
+  for (int it = 0; it < 4; it++) {
+    const double Z = std::sqrt(EB + bound + epsw) * (1.0 + 1e-6) + eta;
+    bound = 2.0 * (u * 1.01 * (Z * Z + EB + bound + epsw) + 2.0 * Z * eta + epsw +
+                   2.0 * u64 * 1.01 * (EB + bound));
+  }
+  if (!(bound < 0.25 * EB)) return false;
+  Bx.bnd = Bw.bnd;
+  Bx.bnd.eps = bound;
+  EdgeF C, A;
+  C.resize(nedges);
+  A.resize(nedges);
+  for (int k = 0; k < nedges; k++) {
+    const double e = Bx.E[k];
+    if (e == 0.0) {
+      C[k] = A[k] = -FLT_MAX;
+      continue;
+    }
+    C[k] = f32_down(e - bound);
+    A[k] = f32_up(e + bound);
+  }
+  bool ok = false;
+  for (int shift = 18; shift <= 23 && !ok; shift++) {
+    ok = build_table(C, A, shift, Bx.t32);
+    if (ok) Bx.shift = shift;
+  }
+  if (!ok) return false;
+  Bx.AB32 = A[nb];
+  Bx.C32 = C;
+  Bx.A32 = A;
+  return true;
 }
 
 // The binning of the last call on this thread, reused while its inputs are
@@ -1565,6 +1619,12 @@ struct cp_plan {
   int count_mode = CP_ORDERED;
   int noprune = 0;
   int tuned = 0;                 // as cp_stats.tuned
+  // xi and w_p in one launch (binary32): the w_p batch's build and pair
+  // launch serve both statistics; xi keeps only its histogram
+  bool fused = false;
+  cp::Binning xbin;              // xi decision table of the fused estimate
+  uint2 *d_tabx = nullptr;
+  double *d_Ex = nullptr;
   void *mem = nullptr;
   hipStream_t cap = nullptr;
   hipStream_t last = nullptr;    // stream of the last execute (results and stats sync it)
@@ -1725,6 +1785,13 @@ static int batch_enqueue(cp_plan &pl, Batch &b, hipStream_t st) {
   auto blocks = [](int64_t n, int per, int cap) {
     return (int)std::min<int64_t>(std::max<int64_t>((n + per - 1) / per, 1), cap);
   };
+  if (pl.fused && &b == &pl.xi) {
+    // the fused w_p launch fills xi's histogram: clear it and xi's flag
+    hipLaunchKernelGGL(k_fill_u64, dim3(blocks((int64_t)b.nout * nm, 256, 1024)), dim3(256), 0,
+                       st, b.d_hist, (int64_t)b.nout * nm);
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, b.d_err, (int64_t)1, 0);
+    return hipGetLastError() == hipSuccess ? CP_OK : fail(CP_ERR_DEVICE, "launch failed");
+  }
   hipLaunchKernelGGL(k_fill_i32, dim3(blocks(b.ncell_tot * kCountStride, 256, 8192)), dim3(256), 0,
                      st, b.S.ccount, b.ncell_tot * kCountStride, 0);
   hipLaunchKernelGGL(k_fill_u64, dim3(blocks((int64_t)b.nout * nm, 256, 1024)), dim3(256), 0, st,
@@ -1752,7 +1819,8 @@ static int batch_enqueue(cp_plan &pl, Batch &b, hipStream_t st) {
                      b.d_segs + nm, 1, b.S.tsum);
   hipLaunchKernelGGL(k_tiles, dim3(tb), dim3(256), 0, st, b.d_geom, nm, b.S.cstart, b.d_maxspan,
                      b.d_col_prefix, b.S.colcnt, b.S.coloff, b.S.tiles, 1);
-  return launch_pairs(st, b.mode, b.prec, 0, b.P, b.lds, b.nwaves);
+  return launch_pairs(st, (pl.fused && &b == &pl.wp) ? WPXI : b.mode, b.prec, 0, b.P, b.lds,
+                      b.nwaves);
 }
 
 // Enqueue one evaluation.  With timing events (eager mode only) the xi and
@@ -1872,9 +1940,35 @@ int cp_plan_create(const cp_points *mocks, int nmocks, const double *xi_edges, i
       cp_plan_destroy(pl);
       return rc;
     }
+    // xi and w_p in one launch (binary32): every xi pair must lie in the w_p
+    // search (xi R_max at most r_p,max and pi_max); CP_PLAN_FUSED=0 keeps two
+    const char *fe = getenv("CP_PLAN_FUSED");
+    if (xi_edges && wp_edges && pl->xi.prec == F32R && pl->wp.prec == F32R &&
+        !(fe && fe[0] == '0') && xi_edges[xi_nedges - 1] <= wp_edges[wp_nedges - 1] &&
+        xi_edges[xi_nedges - 1] <= pimax &&
+        make_binning_wpxi(xi_edges, xi_nedges, pl->wp.B, pl->xbin)) {
+      Batch &b = pl->wp;
+      const int n32 = (int)b.B.t32.e.size(), n64 = (int)b.B.t64.e.size();
+      const int nx = (int)pl->xbin.t32.e.size(), nbx = xi_nedges - 1;
+      b.wpc = wp_copies(WPXI, F32R, 0, n32, n64, b.nb, b.npi, nx, nbx);
+      const LdsLayout LY = lds_layout(WPXI, F32R, 0, n32, n64, b.nb, b.npi, b.wpc, nx, nbx);
+      b.nwaves = pick_waves(LY, &b.lds, b.waves_most);
+      if (b.nwaves) pl->fused = true;
+      else {   // back to two launches
+        const LdsLayout L2 = lds_layout(WP, F32R, 0, n32, n64, b.nb, b.npi, 1);
+        b.wpc = 1;
+        b.nwaves = pick_waves(L2, &b.lds, b.waves_most);
+      }
+    }
+    auto carve_fused = [&](Carver &cv) {
+      if (!pl->fused) return;
+      pl->d_tabx = cv.take<uint2>(pl->xbin.t32.e.size());
+      pl->d_Ex = cv.take<double>(xi_nedges);
+    };
     Carver dry(nullptr, true);
     batch_carve(dry, *pl, pl->xi);
     batch_carve(dry, *pl, pl->wp);
+    carve_fused(dry);
     if (hipMalloc(&pl->mem, dry.off + 256) != hipSuccess) {
       pl->mem = nullptr;
       cp_plan_destroy(pl);
@@ -1883,9 +1977,31 @@ int cp_plan_create(const cp_points *mocks, int nmocks, const double *xi_edges, i
     Carver cv(pl->mem, false);
     batch_carve(cv, *pl, pl->xi);
     batch_carve(cv, *pl, pl->wp);
+    carve_fused(cv);
     if ((rc = batch_upload(*pl, pl->xi)) || (rc = batch_upload(*pl, pl->wp))) {
       cp_plan_destroy(pl);
       return rc;
+    }
+    if (pl->fused) {
+      const Binning &X = pl->xbin;
+      if (hipMemcpy(pl->d_tabx, X.t32.e.data(), 8 * X.t32.e.size(), hipMemcpyHostToDevice) !=
+              hipSuccess ||
+          hipMemcpy(pl->d_Ex, X.E.data(), 8 * (size_t)xi_nedges, hipMemcpyHostToDevice) !=
+              hipSuccess) {
+        cp_plan_destroy(pl);
+        return fail(CP_ERR_DEVICE, "plan upload failed");
+      }
+      PairParams &P = pl->wp.P;
+      P.wpc = pl->wp.wpc;
+      P.tabx = pl->d_tabx;
+      P.tabx_lo = X.t32.lo;
+      P.tabx_hi = X.t32.hi;
+      P.tabx_shift = X.shift;
+      P.Ex = pl->d_Ex;
+      P.nbx = xi_nedges - 1;
+      P.AB32x = X.AB32;
+      P.histx = pl->xi.d_hist;
+      P.histx_stride = pl->xi.nout;
     }
     for (auto &e : pl->ev) {
       if (hipEventCreate(&e) != hipSuccess) {
@@ -1953,15 +2069,18 @@ int cp_plan_results(cp_plan *pl, uint64_t *xi_npairs, uint64_t *wp_npairs) {
     HIPCHK(hipMemcpy(&f, b.d_err, sizeof(int), hipMemcpyDeviceToHost));
     flags |= f;
     if (f) continue;
-    // every queue item must have been taken (as for single calls)
-    std::vector<unsigned long long> st(kStatWords);
-    HIPCHK(hipMemcpy(st.data(), b.d_stats, sizeof(unsigned long long) * kStatWords,
-                     hipMemcpyDeviceToHost));
-    const int64_t nitems = (int64_t)st[4] * b.P.nsplit;
-    for (int k = 0; k < kQueues; k++) {
-      const int64_t len = nitems * (k + 1) / kQueues - nitems * k / kQueues;
-      if (st[5 + (size_t)k * kQStride] < (unsigned long long)len)
-        return fail(CP_ERR_INTERNAL, "work queue not drained");
+    // every queue item must have been taken (as for single calls; a fused
+    // plan's xi shares the w_p launch, checked with w_p)
+    if (!(pl->fused && s == 0)) {
+      std::vector<unsigned long long> st(kStatWords);
+      HIPCHK(hipMemcpy(st.data(), b.d_stats, sizeof(unsigned long long) * kStatWords,
+                       hipMemcpyDeviceToHost));
+      const int64_t nitems = (int64_t)st[4] * b.P.nsplit;
+      for (int k = 0; k < kQueues; k++) {
+        const int64_t len = nitems * (k + 1) / kQueues - nitems * k / kQueues;
+        if (st[5 + (size_t)k * kQStride] < (unsigned long long)len)
+          return fail(CP_ERR_INTERNAL, "work queue not drained");
+      }
     }
     if (!out) continue;
     std::vector<unsigned long long> h((size_t)b.nout * pl->nmock);
@@ -1979,11 +2098,12 @@ int cp_plan_stats(cp_plan *pl, cp_stats *xs, cp_stats *ws) {
   if (!pl) return fail(CP_ERR_INVALID_ARG, "plan is NULL");
   HIPCHK(hipStreamSynchronize(pl->last));
   for (int s = 0; s < 2; s++) {
-    Batch &b = s ? pl->wp : pl->xi;
+    // a fused plan's xi reports the shared w_p launch (grid, work, timing)
+    Batch &b = (s || pl->fused) ? pl->wp : pl->xi;
     cp_stats *o = s ? ws : xs;
     if (!o) continue;
     memset(o, 0, sizeof(*o));
-    if (!b.on) continue;
+    if (!(s ? pl->wp : pl->xi).on) continue;
     unsigned long long st[kStatWords];
     int nt = 0;
     HIPCHK(hipMemcpy(st, b.d_stats, sizeof(st), hipMemcpyDeviceToHost));
@@ -2003,7 +2123,8 @@ int cp_plan_stats(cp_plan *pl, cp_stats *xs, cp_stats *ws) {
     }
     float ms = 0;
     if (pl->timed == 1) {
-      if (hipEventElapsedTime(&ms, pl->ev[s], pl->ev[s + 1]) == hipSuccess) o->ms_pairs = ms;
+      const int si = pl->fused ? 1 : s;
+      if (hipEventElapsedTime(&ms, pl->ev[si], pl->ev[si + 1]) == hipSuccess) o->ms_pairs = ms;
       if (hipEventElapsedTime(&ms, pl->ev[0], pl->ev[2]) == hipSuccess) o->ms_total = ms;
     } else if (pl->timed == 2) {
       if (hipEventElapsedTime(&ms, pl->ev[3], pl->ev[4]) == hipSuccess) o->ms_total = ms;

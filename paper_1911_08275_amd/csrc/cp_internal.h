@@ -68,7 +68,11 @@ bool tune_lookup(const std::string &key, TuneChoice &out);
 void tune_store(const std::string &key, const TuneChoice &t);
 std::string tune_cache_file();
 
-enum Mode { XI = 0, WP = 1 };
+// WPXI: w_p and xi of the same catalogues in one pass over the w_p search
+// (binary32 mode; every xi pair lies inside the w_p cylinder when the xi
+// R_max is at most both r_p,max and pi_max).  Where the kernel tests
+// MODE == XI, WPXI takes the w_p side.
+enum Mode { XI = 0, WP = 1, WPXI = 2 };
 enum Prec { F64 = 0, F32R = 1 };
 
 // Geometry of one catalogue's cell grid.  Cells are ordered x-major, z
@@ -164,6 +168,15 @@ struct PairParams {
   unsigned long long *stats; // kStatWords: candidates, rechecks, cell pairs, pruned,
                              // tile count (written by the pair kernel), queue heads
   int hist_stride;           // nb * npi
+  // xi of a WPXI launch: decision table of s~ = fl32(pi~^2 + rp~^2) (bands
+  // of its own error bound), squared edges, histogram
+  const uint2 *tabx;
+  int tabx_lo, tabx_hi, tabx_shift;
+  const double *Ex;          // nbx + 1
+  int nbx;
+  float AB32x;               // s~ >= AB32x -> certainly >= the last xi edge
+  unsigned long long *histx; // [nmock][nbx]
+  int histx_stride;
 };
 
 } // namespace cp
@@ -191,7 +204,7 @@ __host__ __device__ inline int cell_coord(const GridGeom &g, int a, double v) {
 __host__ __device__ inline size_t align16(size_t v) { return (v + 15) & ~(size_t)15; }
 
 struct LdsLayout {
-  size_t tab32, tab64, E, common, wave_hist, wave_w, wave_list, wave_bytes;
+  size_t tab32, tab64, E, tabx, Ex, common, wave_hist, wave_w, wave_list, wave_histx, wave_bytes;
 };
 
 // Weighted xi with the binary32 filter: the filter needs no decision table
@@ -206,9 +219,12 @@ __host__ __device__ constexpr bool xi_f32_weighted(int mode, int prec, int weigh
 constexpr int kListCap = 64 + 4 * 64;
 
 // wpc: copies of the w_p histogram (and weight sums) per wave, interleaved
-// counter by counter; lane l adds to copy l mod wpc.
+// counter by counter; lane l adds to copy l mod wpc.  nx, nbx: the xi table
+// entries and bins of a WPXI launch (xi rows, one per lane pair, follow the
+// w_p histogram).
 __host__ __device__ inline LdsLayout lds_layout(int mode, int prec, int weighted, int n32, int n64,
-                                               int nb, int npi, int wpc = 1) {
+                                               int nb, int npi, int wpc = 1, int nx = 0,
+                                               int nbx = 0) {
   LdsLayout L;
   size_t off = 0;
   L.tab32 = off;
@@ -218,6 +234,13 @@ __host__ __device__ inline LdsLayout lds_layout(int mode, int prec, int weighted
   off += (size_t)n64 * 8;
   L.E = off;
   off += (size_t)(nb + 1) * 8;
+  L.tabx = off;
+  L.Ex = off;
+  if (mode == WPXI) {
+    off += (size_t)nx * 8;
+    L.Ex = off;
+    off += (size_t)(nbx + 1) * 8;
+  }
   L.common = align16(off);
   const int NS = nb + 2;
   const size_t words = mode == XI ? (size_t)NS * 64 : (size_t)NS * npi * wpc;
@@ -225,7 +248,8 @@ __host__ __device__ inline LdsLayout lds_layout(int mode, int prec, int weighted
   // weight sums are shared by the wave (one row of slots), not lane-private
   L.wave_w = weighted ? (mode == XI ? (size_t)NS * kWStripe : words) * 8 : 0;
   L.wave_list = L.wave_hist + 2 * L.wave_w;
-  L.wave_bytes = L.wave_list + (xi_f32_weighted(mode, prec, weighted) ? (size_t)kListCap * 4 : 0);
+  L.wave_histx = L.wave_list + (xi_f32_weighted(mode, prec, weighted) ? (size_t)kListCap * 4 : 0);
+  L.wave_bytes = L.wave_histx + (mode == WPXI ? (size_t)(nbx + 2) * 32 * 4 : 0);
   return L;
 }
 

@@ -163,9 +163,30 @@ __device__ inline void add_w(double *p, double w, double wr) {
 
 struct WaveArea {
   uint32_t *hist;
+  uint32_t *histx;  // WPXI: the xi counters, one row of slots per lane pair (lane mod 32)
   double *hw;   // weight sums, interleaved: hw[2 i] = sum w, hw[2 i + 1] = sum w r
   uint32_t *list;   // weighted xi, binary32 mode: (tile lane, record) pairs to evaluate
 };
+
+// xi counters rows[s * 32 + c] of slots s = 0 .. nb + 1, one column per
+// lane pair (c = lane mod 32): lane s - 1 takes slot s's wave total, and one
+// atomic instruction adds them all (every wave's totals land in the same few
+// lines of the output, and per-slot atomics from one lane, one memory request
+// each, queued there for tens of microseconds at the end of a launch); then
+// the rows are cleared.
+__device__ inline void flush_xi_rows(uint32_t *rows, unsigned long long *gh, int nb, int lane) {
+  unsigned long long mine = 0;
+  for (int s = 1; s <= nb; s++) {
+    const unsigned long long v =
+        wave_sum_u64(lane < 32 ? (unsigned long long)rows[s * 32 + lane] : 0ull);
+    if (lane == s - 1) mine = v;
+  }
+  if (lane < nb && mine) atomicAdd(gh + lane, mine);
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  if (lane < 32)
+    for (int s = 0; s < nb + 2; s++) rows[s * 32 + lane] = 0u;
+}
 
 template <int MODE, int W>
 __device__ inline void flush_hist(const PairParams &P, WaveArea A, int mock, int lane) {
@@ -224,6 +245,7 @@ __device__ inline void flush_hist(const PairParams &P, WaveArea A, int mock, int
         A.hw[2 * t + 1] = 0.0;
       }
     }
+    if (MODE == WPXI) flush_xi_rows(A.histx, P.histx + (int64_t)mock * P.histx_stride, P.nbx, lane);
   }
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -639,6 +661,70 @@ __device__ inline void loop_wp_f32(const PairParams &P, WaveArea A, const LanePt
   nrechk += nunc;
 }
 
+// w_p and xi in one pass (WPXI, unweighted): the w_p decisions of
+// loop_wp_f32, and for xi the estimate s~ = fl32(pi~^2 + rp~^2) from the same
+// binary32 values, decided through its own table (bands of the WPXI error
+// bound); an uncertain xi pair is re-evaluated in binary64.  Pairs are
+// counted once for each statistic they belong to.
+template <bool OWN>
+__device__ inline void loop_wpxi_f32(const PairParams &P, WaveArea A, const LanePt &L, int lane,
+                                     float rx, float ry, float rz, float ra, const Unit &U,
+                                     const uint2 *tab32, const double *sE, const uint2 *tabx,
+                                     const double *sEx, uint32_t &nrechk) {
+  const int npi = P.npi, wpc = P.wpc, lo = P.tab32_lo, sh = P.tab_shift;
+  const int row = npi * wpc;
+  const int base = lane & (wpc - 1);
+  const uint2 *tb = tab32 - lo;
+  const float AB = P.AB32, phi = P.pi_hi32, plo = P.pi_lo32, inv = P.inv_dpi32;
+  const float pd = P.pi_delta, pd1 = 1.0f - P.pi_delta;
+  const int lox = P.tabx_lo, shx = P.tabx_shift, nbx = P.nbx;
+  const uint2 *tbx = tabx - lox;
+  const float ABx = P.AB32x;
+  const int xc = lane & 31;
+  uint32_t nunc = 0;
+  stream_f32(U.strm, U.jb, U.je, [&](int j, float qx, float qy, float qz, float qw) {
+    const float v = __builtin_fmaf(ry, qy, __builtin_fmaf(rx, qx, ra)) + qw;
+    const float pz = fabsf(qz - rz);
+    const bool ok = OWN ? (j > L.iloc) : true;
+    if (ok && v < AB && pz < phi) {
+      const uint2 e = tb[max(__float_as_int(v) >> sh, lo)];
+      const float f = pz * inv;
+      const float fl = floorf(f);
+      const float fr = f - fl;
+      const bool ch = v >= __uint_as_float(e.y);
+      const bool unc = (v >= __uint_as_float(e.x) && !ch) || fr < pd || fr > pd1 || pz >= plo;
+      if (unc) {
+        recheck_wp<true>(P, A, L, U, j, sE, base);
+        nunc++;
+      } else {
+        const int slot = (int)(e.y & 63u) - 1 + (ch ? 1 : 0);
+        const int l = min((int)fl, npi - 1);
+        atomicAdd(&A.hist[__umul24(slot, row) + __umul24(l, wpc) + base], 1u);
+      }
+    }
+    const float sx = __builtin_fmaf(pz, pz, v);
+    if (ok && sx < ABx) {
+      const uint2 e = tbx[max(__float_as_int(sx) >> shx, lox)];
+      const bool ch = sx >= __uint_as_float(e.y);
+      int slot;
+      if (sx >= __uint_as_float(e.x) && !ch) {
+        // binary64 re-evaluation (the reference separation)
+        sdouble *DP = (sdouble *)U.pos;
+        const int wz[3] = {0, 0, 0};
+        double dx, dy, dz;
+        ref_sep<true, false>(L.x, L.y, L.z, DP[4 * j], DP[4 * j + 1], DP[4 * j + 2], U.S, wz, 0.0,
+                             0.0, dx, dy, dz);
+        slot = exact_slot(sEx, nbx, (dx * dx + dy * dy) + dz * dz);
+        nunc++;
+      } else {
+        slot = (int)(e.y & 63u) - 1 + (ch ? 1 : 0);
+      }
+      atomicAdd(&A.histx[slot * 32 + xc], 1u);
+    }
+  });
+  nrechk += nunc;
+}
+
 // wp, weighted: every in-range pair is evaluated in binary64 for its rp.
 template <bool OWN, bool SHIFT>
 __device__ inline void loop_wp_f32_w(const PairParams &P, WaveArea A, const LanePt &L, int lane,
@@ -1035,18 +1121,29 @@ void k_pairs(PairParams P) {
   const int wid = threadIdx.x >> 6;
   const int n32 = (PREC == F32R && !xi_f32_weighted(MODE, PREC, W)) ? P.tab32_hi - P.tab32_lo + 1 : 0;
   const int n64 = P.tab64_hi - P.tab64_lo + 1;
-  const LdsLayout LY = lds_layout(MODE, PREC, W, n32, n64, P.nb, P.npi, P.wpc);
+  const int nx = MODE == WPXI ? P.tabx_hi - P.tabx_lo + 1 : 0;
+  const LdsLayout LY = lds_layout(MODE, PREC, W, n32, n64, P.nb, P.npi, P.wpc, nx, P.nbx);
   uint2 *tab32 = (uint2 *)(smem + LY.tab32);
   uint2 *tab64 = (uint2 *)(smem + LY.tab64);
   double *sE = (double *)(smem + LY.E);
   for (int t = threadIdx.x; t < n32; t += blockDim.x) tab32[t] = P.tab32[t];
   for (int t = threadIdx.x; t < n64; t += blockDim.x) tab64[t] = P.tab64[t];
   for (int t = threadIdx.x; t <= P.nb; t += blockDim.x) sE[t] = P.E[t];
+  uint2 *tabx = (uint2 *)(smem + LY.tabx);
+  double *sEx = (double *)(smem + LY.Ex);
+  if (MODE == WPXI) {
+    for (int t = threadIdx.x; t < nx; t += blockDim.x) tabx[t] = P.tabx[t];
+    for (int t = threadIdx.x; t <= P.nbx; t += blockDim.x) sEx[t] = P.Ex[t];
+  }
   unsigned char *wb = smem + LY.common + (size_t)wid * LY.wave_bytes;
   WaveArea A;
   A.hist = (uint32_t *)wb;
   A.hw = (double *)(wb + LY.wave_hist);
   A.list = (uint32_t *)(wb + LY.wave_list);
+  A.histx = (uint32_t *)(wb + LY.wave_histx);
+  if (MODE == WPXI) {
+    for (int t = lane; t < (P.nbx + 2) * 32; t += 64) A.histx[t] = 0u;
+  }
   const int NS = P.nslots;
   const int hwords = MODE == XI ? NS * 64 : NS * P.npi * P.wpc;
   const int wwords = MODE == XI ? NS * kWStripe : hwords;
@@ -1339,6 +1436,10 @@ void k_pairs(PairParams P) {
               if (own) loop_xi_f32<true, true>(P, A, L, lane, rxf, ryf, rzf, ra, U, tab32, sE, nrechk);
               else loop_xi_f32<false, true>(P, A, L, lane, rxf, ryf, rzf, ra, U, tab32, sE, nrechk);
             }
+          } else if (MODE == WPXI) {
+            const float ra = __builtin_fmaf(ryf, ryf, rxf * rxf);
+            if (own) loop_wpxi_f32<true>(P, A, L, lane, rxf, ryf, rzf, ra, U, tab32, sE, tabx, sEx, nrechk);
+            else loop_wpxi_f32<false>(P, A, L, lane, rxf, ryf, rzf, ra, U, tab32, sE, tabx, sEx, nrechk);
           } else if (!W) {
             const float ra = __builtin_fmaf(ryf, ryf, rxf * rxf);
             if (own) loop_wp_f32<true, true>(P, A, L, lane, rxf, ryf, rzf, ra, U, tab32, sE, nrechk);
@@ -1407,5 +1508,6 @@ template __global__ void k_pairs<WP, F32R, 0>(PairParams);
 template __global__ void k_pairs<WP, F32R, 1>(PairParams);
 template __global__ void k_pairs<WP, F64, 0>(PairParams);
 template __global__ void k_pairs<WP, F64, 1>(PairParams);
+template __global__ void k_pairs<WPXI, F32R, 0>(PairParams);
 
 } // namespace cp

@@ -572,6 +572,46 @@ def test_plan_matches_oracle(native):
         plan.close()
 
 
+@pytest.mark.parametrize("case", ["fused", "xi_beyond_pimax"])
+def test_plan_fused_xi_wp(native, monkeypatch, case):
+    """Binary32 plans count xi and w_p in one launch over the w_p search when
+    every xi pair lies inside it (xi R_max <= r_p,max and <= pi_max): the
+    results equal the two-launch plan (CP_PLAN_FUSED=0), the oracle and single
+    calls, bit for bit, own cells and exact z ties included.  With xi R_max
+    above pi_max the plan keeps two launches and agrees as well."""
+    cats = _mock_set()
+    # exact z ties and a dense cluster: own-cell pairs and the xi bands
+    cats[0].z[::5] = cats[0].z[0]
+    xe = synth.log_edges(0.1, 25.0, 14)
+    we = synth.log_edges(0.1, 25.0, 14)
+    pimax = 40.0 if case == "fused" else 20.0
+    devs = [native.to_device(c) for c in cats]
+    _say("plan fused", case)
+    out = {}
+    for fused in ("1", "0"):
+        monkeypatch.setenv("CP_PLAN_FUSED", fused)
+        plan = native.Plan(devs, xi_edges=xe, wp_edges=we, pimax=pimax, npibins=40,
+                           precision="fp32", periodic=True, boxsize=420.0, refine=(2, 2, 2))
+        plan.execute()
+        out[fused] = plan.results()
+        sx, sw = plan.stats()
+        assert sx["precision"] == "fp32" and sw["precision"] == "fp32"
+        plan.close()
+    assert (out["1"][0] == out["0"][0]).all()
+    assert (out["1"][1] == out["0"][1]).all()
+    xi, wp = out["1"]
+    for m in (0, 2, 5):
+        _check(type("G", (), {"npairs": xi[m]})(), oracle.xi(cats[m], xe, True, 420.0))
+        _check(type("G", (), {"npairs": wp[m]})(),
+               oracle.wp(cats[m], we, pimax, 40, periodic=True, box=420.0))
+    for m in range(len(cats)):
+        s = native.countpairs_xi(devs[m], xe, precision="fp32", periodic=True, boxsize=420.0)
+        assert (s.npairs == xi[m]).all(), m
+        s = native.countpairs_wp(devs[m], we, pimax, 40, precision="fp32", periodic=True,
+                                 boxsize=420.0)
+        assert (s.npairs == wp[m]).all(), m
+
+
 def test_plan_pruning_off_equals_on(native):
     """The plan path with the bounding-box tests switched off gives the same
     counts for every catalogue and statistic."""
