@@ -70,6 +70,17 @@ __device__ inline double uni_d(double v) {
   return __longlong_as_double(uni64(__double_as_longlong(v)));
 }
 
+// A wave-uniform value held in a VGPR (every lane the same): loop constants
+// of the heavier loops live there, so the SGPRs stay free for the streamed
+// records (constants kept in SGPRs were spilled to VGPR lanes and read back
+// with v_readlane on every record).
+__device__ inline int in_vgpr(int v) {
+  int r;
+  asm("v_mov_b32 %0, %1" : "=v"(r) : "s"(v));
+  return r;
+}
+__device__ inline float in_vgpr(float v) { return __int_as_float(in_vgpr(__float_as_int(v))); }
+
 // Slot of a binary64 squared separation: 0 below E_0, k + 1 for bin k,
 // nb + 1 at or above E_nb (the reference half-open rule).
 __device__ inline int exact_slot(const double *E, int nb, double s) {
@@ -628,12 +639,14 @@ template <bool OWN, bool SHIFT>
 __device__ inline void loop_wp_f32(const PairParams &P, WaveArea A, const LanePt &L, int lane,
                                    float rx, float ry, float rz, float ra, const Unit &U,
                                    const uint2 *tab32, const double *sE, uint32_t &nrechk) {
-  const int npi = P.npi, wpc = P.wpc, lo = P.tab32_lo, sh = P.tab_shift;
+  const int npi = in_vgpr(P.npi), wpc = in_vgpr(P.wpc), lo = in_vgpr(P.tab32_lo);
+  const int sh = in_vgpr(P.tab_shift);
   const int row = npi * wpc;                       // histogram words per slot
   const int base = lane & (wpc - 1);
-  const uint2 *tb = tab32 - lo;
-  const float AB = P.AB32, phi = P.pi_hi32, plo = P.pi_lo32, inv = P.inv_dpi32;
-  const float pd = P.pi_delta, pd1 = 1.0f - P.pi_delta;
+  const uint2 *tb = tab32 - P.tab32_lo;
+  const float AB = in_vgpr(P.AB32), phi = in_vgpr(P.pi_hi32), plo = in_vgpr(P.pi_lo32);
+  const float inv = in_vgpr(P.inv_dpi32);
+  const float pd = in_vgpr(P.pi_delta), pd1 = in_vgpr(1.0f - P.pi_delta);
   uint32_t nunc = 0;
   stream_f32(U.strm, U.jb, U.je, [&](int j, float qx, float qy, float qz, float qw) {
     const float v = __builtin_fmaf(ry, qy, __builtin_fmaf(rx, qx, ra)) + qw;
@@ -671,15 +684,17 @@ __device__ inline void loop_wpxi_f32(const PairParams &P, WaveArea A, const Lane
                                      float rx, float ry, float rz, float ra, const Unit &U,
                                      const uint2 *tab32, const double *sE, const uint2 *tabx,
                                      const double *sEx, uint32_t &nrechk) {
-  const int npi = P.npi, wpc = P.wpc, lo = P.tab32_lo, sh = P.tab_shift;
+  const int npi = in_vgpr(P.npi), wpc = in_vgpr(P.wpc), lo = in_vgpr(P.tab32_lo);
+  const int sh = in_vgpr(P.tab_shift);
   const int row = npi * wpc;
   const int base = lane & (wpc - 1);
-  const uint2 *tb = tab32 - lo;
-  const float AB = P.AB32, phi = P.pi_hi32, plo = P.pi_lo32, inv = P.inv_dpi32;
-  const float pd = P.pi_delta, pd1 = 1.0f - P.pi_delta;
-  const int lox = P.tabx_lo, shx = P.tabx_shift, nbx = P.nbx;
-  const uint2 *tbx = tabx - lox;
-  const float ABx = P.AB32x;
+  const uint2 *tb = tab32 - P.tab32_lo;
+  const float AB = in_vgpr(P.AB32), phi = in_vgpr(P.pi_hi32), plo = in_vgpr(P.pi_lo32);
+  const float inv = in_vgpr(P.inv_dpi32);
+  const float pd = in_vgpr(P.pi_delta), pd1 = in_vgpr(1.0f - P.pi_delta);
+  const int lox = in_vgpr(P.tabx_lo), shx = in_vgpr(P.tabx_shift), nbx = P.nbx;
+  const uint2 *tbx = tabx - P.tabx_lo;
+  const float ABx = in_vgpr(P.AB32x);
   const int xc = lane & 31;
   uint32_t nunc = 0;
   stream_f32(U.strm, U.jb, U.je, [&](int j, float qx, float qy, float qz, float qw) {
