@@ -570,50 +570,14 @@ __device__ inline void loop_xi_f32(const PairParams &P, WaveArea A, const LanePt
   nrechk += nunc;
 }
 
-// wp, binary32 filter: the rp^2 estimate goes through the table, |dz| is
-// binned by multiplying with 1/dpi, and a pair whose fraction lies within
-// pi_delta of a pi edge, or whose |dz| is near pi_max, is uncertain.
-// Line-of-sight part of a binary32 wp decision: pi~ = |qz - rz| (cell-local
-// coordinates), its bin, whether it is surely below pi_max (inr: not surely
-// above), and whether binary32 cannot settle it (within the pi error bound
-// of a pi edge or of pi_max).
-struct WpPi {
-  bool inr, unc;
-  int l;
-};
-__device__ inline WpPi wp_pi(const PairParams &P, float rz, float qz) {
-  const float pz = fabsf(qz - rz);
-  const float f = pz * P.inv_dpi32;
-  const float fl = floorf(f);
-  const float fr = f - fl;
-  WpPi r;
-  r.l = min((int)fl, P.npi - 1);
-  r.inr = pz < P.pi_hi32;
-  r.unc = r.inr && ((fr < P.pi_delta) || (fr > 1.0f - P.pi_delta) || (pz >= P.pi_lo32));
-  return r;
-}
-
-struct WpHit {
-  bool inr, unc;
-  int slot, l;
-};
-template <bool OWN>
-__device__ inline WpHit wp_decide(const PairParams &P, const uint2 *tab32, const LanePt &L,
-                                  float rx, float ry, float rz, float ra, int j, float qx,
-                                  float qy, float qz, float qw) {
-  float v = __builtin_fmaf(rx, qx, ra);
-  v = __builtin_fmaf(ry, qy, v);
-  const float s = v + qw;
-  const WpPi q = wp_pi(P, rz, qz);
-  WpHit r;
-  r.inr = (s < P.AB32) && q.inr;
-  if (OWN) r.inr = r.inr && (j > L.iloc);
-  const TabHit h = tab_lookup(tab32, P.tab32_lo, P.tab32_hi, P.tab_shift, s);
-  r.l = q.l;
-  r.slot = h.slot;
-  r.unc = r.inr && (h.unc || q.unc);
-  return r;
-}
+// wp, binary32 filter (the loops below): the r_p^2 estimate v~ (Gram form in
+// the streamed cell's frame) goes through the decision table, the line of
+// sight pi~ = |qz - rz| (cell-local coordinates) is binned by multiplying
+// with 1/dpi, and a pair is in range when v~ < AB32 and pi~ < pi_hi32 (not
+// surely beyond r_p,max or pi_max); it is uncertain when v~ lies in an edge's
+// band, when the fraction of pi~ / dpi lies within pi_delta of a pi edge, or
+// when pi~ >= pi_lo32 (near pi_max).  v~ < AB32 keeps the table index at or
+// below the table's top, so the index is clamped below only.
 
 // Binary64 re-evaluation of one uncertain wp pair (unweighted).
 template <bool SHIFT>
@@ -632,9 +596,7 @@ __device__ inline void recheck_wp(const PairParams &P, WaveArea A, const LanePt 
 }
 
 // wp, unweighted: certain pairs are counted at once, uncertain ones
-// re-evaluated in binary64 on the spot (as in the general xi loop).  The same
-// decisions as wp_decide, with the binary32 r_p^2 and |dz| formed once and
-// the table index clamped below only (v < AB32 keeps it inside the table).
+// re-evaluated in binary64 on the spot (as in the general xi loop).
 template <bool OWN, bool SHIFT>
 __device__ inline void loop_wp_f32(const PairParams &P, WaveArea A, const LanePt &L, int lane,
                                    float rx, float ry, float rz, float ra, const Unit &U,
@@ -745,29 +707,46 @@ template <bool OWN, bool SHIFT>
 __device__ inline void loop_wp_f32_w(const PairParams &P, WaveArea A, const LanePt &L, int lane,
                                      float rx, float ry, float rz, float ra, const Unit &U,
                                      const uint2 *tab32, const double *sE, uint32_t &nrechk) {
-  const int nb = P.nb, npi = P.npi, wpc = P.wpc, cpy = lane & (wpc - 1);
+  const int nb = P.nb;
+  const int npi = in_vgpr(P.npi), wpc = in_vgpr(P.wpc), lo = in_vgpr(P.tab32_lo);
+  const int sh = in_vgpr(P.tab_shift);
+  const int row = npi * wpc, cpy = lane & (wpc - 1);
+  const uint2 *tb = tab32 - P.tab32_lo;
+  const float AB = in_vgpr(P.AB32), phi = in_vgpr(P.pi_hi32), plo = in_vgpr(P.pi_lo32);
+  const float inv = in_vgpr(P.inv_dpi32);
+  const float pd = in_vgpr(P.pi_delta), pd1 = in_vgpr(1.0f - P.pi_delta);
   const int wrapax[3] = {0, 0, 0};
   stream_w(U.strm, U.pos, U.jb, U.je,
            [&](int j, float qx, float qy, float qz, float qw, double ux, double uy, double uz,
                double uw) {
-             const WpHit h = wp_decide<OWN>(P, tab32, L, rx, ry, rz, ra, j, qx, qy, qz, qw);
-             if (h.inr) {
+             const float v = __builtin_fmaf(ry, qy, __builtin_fmaf(rx, qx, ra)) + qw;
+             const float pz = fabsf(qz - rz);
+             bool inr = (v < AB) && (pz < phi);
+             if (OWN) inr = inr && (j > L.iloc);
+             if (inr) {
+               const uint2 e = tb[max(__float_as_int(v) >> sh, lo)];
+               const float f = pz * inv;
+               const float fl = floorf(f);
+               const float fr = f - fl;
+               const bool ch = v >= __uint_as_float(e.y);
+               const bool unc =
+                   (v >= __uint_as_float(e.x) && !ch) || fr < pd || fr > pd1 || pz >= plo;
                double dx, dy, dz;
                ref_sep<SHIFT, false>(L.x, L.y, L.z, ux, uy, uz, U.S, wrapax, 0.0, 0.0, dx, dy,
                                      dz);
-               int sl = h.slot, ll = h.l;
+               int sl = (int)(e.y & 63u) - 1 + (ch ? 1 : 0), ll = min((int)fl, npi - 1);
                bool keep = true;
-               if (h.unc) {
+               if (unc) {
                  nrechk++;
                  const double rp2 = dx * dx + dy * dy;
                  const double pz64 = fabs(dz);
                  keep = pz64 < P.pimax && rp2 < P.EB;
                  sl = exact_slot(sE, nb, rp2);
-                 ll = exact_pibin(pz64, P.dpi, P.inv_dpi, npi);
+                 ll = exact_pibin(pz64, P.dpi, P.inv_dpi, P.npi);
                }
                if (keep) {
                  const double ww = L.w * uw;
-                 const int c = (sl * npi + ll) * wpc + cpy;
+                 const int c = __umul24(sl, row) + __umul24(ll, wpc) + cpy;
                  atomicAdd(&A.hist[c], 1u);
                  add_w(A.hw + 2 * c, ww, ww * sep_sqrt(__builtin_fma(dx, dx, dy * dy)));
                }
