@@ -22,6 +22,11 @@ __global__ void k_bbox_partial(PointsDev a, PointsDev b, double *out, int *err);
 __global__ void k_bbox_final(const double *part, int nblk, double *out);
 __global__ void k_fill_i32(int *p, int64_t n, int v);
 __global__ void k_fill2_i32(int *a, int64_t na, int *b, int64_t nb);
+__global__ void k_colcount(const PointsDev *pts, const GridGeom *geom, int *mat, int *err);
+__global__ void k_colscatter(const PointsDev *pts, const GridGeom *geom, const int *off,
+                             double4 *out);
+__global__ void k_colcells(const GridGeom *geom, const int *off, int stride, const double4 *colgrp,
+                           double4 *grp, int *cstart);
 __global__ void k_fill_u64(unsigned long long *p, int64_t n);
 __global__ void k_fill_f64(double *p, int64_t n);
 __global__ void k_scan_sums(const int *in, const ScanSeg *segs, int nseg, int *tsum);
@@ -449,6 +454,7 @@ struct Carver {
 struct SetBufs {
   int *ccount, *cstart, *cid, *rank, *colcnt, *coloff;
   int *tsum;            // tile totals of the segmented scans
+  int *colmat;          // column x block counts of the LDS column grouping
   double4 *pos, *grp;   // grp: points grouped by cell before the z order
   float4 *strm;
   CellBox *cbox;
@@ -459,7 +465,9 @@ static void carve_set(Carver &cv, SetBufs &S, int64_t n, int64_t ncell, int64_t 
                       bool want_tiles, int64_t maxtiles) {
   S.ccount = cv.take<int>(ncell * kCountStride);
   S.cstart = cv.take<int>(ncell + 1);
-  S.tsum = cv.take<int>(std::max(scan_tiles(ncell), scan_tiles(ncol)));
+  const int64_t nmat = ncol <= kColLds ? ncol * kColBlocks : 0;
+  S.tsum = cv.take<int>(std::max({scan_tiles(ncell), scan_tiles(ncol), scan_tiles(nmat)}));
+  S.colmat = cv.take<int>(nmat + 1);
   S.cid = cv.take<int>(n > 0 ? n : 1);
   S.rank = cv.take<int>(n > 0 ? n : 1);
   // +8 records: the pair kernels prefetch scalar loads past a cell's end
@@ -467,21 +475,18 @@ static void carve_set(Carver &cv, SetBufs &S, int64_t n, int64_t ncell, int64_t 
   S.grp = cv.take<double4>(n > 0 ? n : 1);
   S.strm = cv.take<float4>(n + 8);
   S.cbox = cv.take<CellBox>(ncell);
-  if (want_tiles) {
-    S.colcnt = cv.take<int>(ncol + 1);
-    S.coloff = cv.take<int>(ncol + 1);
-    S.tiles = cv.take<Tile>(maxtiles);
-  } else {
-    S.colcnt = S.coloff = nullptr;
-    S.tiles = nullptr;
-  }
+  // column counts and offsets: the column grouping of every set, the tile
+  // queue of the tiled set
+  S.colcnt = cv.take<int>(ncol + 1);
+  S.coloff = cv.take<int>(ncol + 1);
+  S.tiles = want_tiles ? cv.take<Tile>(maxtiles) : nullptr;
 }
 
 // Small per-call records uploaded in one copy.
 struct Smalls {
   GridGeom geom[2];
   PointsDev pts[2];
-  ScanSeg seg[3];
+  ScanSeg seg[4];   // cells, columns, column x block matrix of set 1 and of set 2
   int64_t win_prefix[2][2];   // z-order windows of set 1 and set 2
   int64_t col_prefix[2];
   int maxspan[2];
@@ -565,26 +570,48 @@ static int64_t max_tiles_bound(int64_t n, int64_t ncell, int64_t ncol) {
 static int launch_build(hipStream_t st, const PointsDev *d_pts, const GridGeom *d_geom,
                         const SetBufs &S, int64_t n, int64_t ncell, int64_t ncol, int mode,
                         const ScanSeg *d_seg_cells, const ScanSeg *d_seg_cols,
+                        const ScanSeg *d_seg_mat,
                         const int64_t *d_win_prefix, const int64_t *d_col_prefix,
                         const int *d_maxspan, int *d_err, bool tiles, int *zero = nullptr,
                         int64_t zero_words = 0) {
-  // the cell counters (and the caller's extra range) cleared by one launch
-  const int64_t nfill = ncell * kCountStride;
-  const int fb = (int)std::min<int64_t>(std::max<int64_t>((nfill + zero_words + 255) / 256, 1), 4096);
   (void)hipGetLastError();
-  hipLaunchKernelGGL(k_fill2_i32, dim3(fb), dim3(256), 0, st, S.ccount, nfill, zero, zero_words);
-  const int ab = (int)std::min<int64_t>(std::max<int64_t>((n + 255) / 256, 1), 8192);
-  if (n > 0)
-    hipLaunchKernelGGL(k_assign, dim3(ab, 1), dim3(256), 0, st, d_pts, d_geom, S.ccount, S.cid,
-                       S.rank, d_err);
-  const unsigned sc = (unsigned)scan_tiles(ncell);
-  if (sc > 1)   // a single tile needs no tile totals
-    hipLaunchKernelGGL(k_scan_sums, dim3(sc), dim3(256), 0, st, S.ccount, d_seg_cells, 1, S.tsum);
-  hipLaunchKernelGGL(k_scan_apply, dim3(sc), dim3(256), 0, st, S.ccount, S.cstart, d_seg_cells, 1,
-                     S.tsum);
-  if (n > 0)
-    hipLaunchKernelGGL(k_group, dim3(ab, 1), dim3(256), 0, st, d_pts, d_geom, S.cstart, S.cid,
-                       S.rank, S.grp);
+  const char *ce = getenv("CP_BUILD_COLUMNS");
+  if (n > 0 && ncol <= kColLds && !(ce && ce[0] == '0')) {
+    // grouping through LDS column histograms: the column x block counts in
+    // colmat (scanned in place), column order in pos before the z pass
+    // overwrites it
+    if (zero_words)
+      hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)std::min<int64_t>((zero_words + 255) / 256, 64)),
+                         dim3(256), 0, st, zero, zero_words, 0);
+    const int nb1 = col_blocks(n);
+    hipLaunchKernelGGL(k_colcount, dim3(nb1), dim3(1024), 0, st, d_pts, d_geom, S.colmat, d_err);
+    const unsigned tm = (unsigned)scan_tiles(ncol * nb1);
+    if (tm > 1)
+      hipLaunchKernelGGL(k_scan_sums, dim3(tm), dim3(256), 0, st, S.colmat, d_seg_mat, 1, S.tsum);
+    hipLaunchKernelGGL(k_scan_apply, dim3(tm), dim3(256), 0, st, S.colmat, S.colmat, d_seg_mat, 1,
+                       S.tsum);
+    hipLaunchKernelGGL(k_colscatter, dim3(nb1), dim3(1024), 0, st, d_pts, d_geom, S.colmat, S.pos);
+    hipLaunchKernelGGL(k_colcells, dim3((unsigned)std::min<int64_t>(ncol, 8192)), dim3(256), 0, st,
+                       d_geom, S.colmat, nb1, S.pos, S.grp, S.cstart);
+  } else {
+    // the cell counters (and the caller's extra range) cleared by one launch
+    const int64_t nfill = ncell * kCountStride;
+    const int fb =
+        (int)std::min<int64_t>(std::max<int64_t>((nfill + zero_words + 255) / 256, 1), 4096);
+    hipLaunchKernelGGL(k_fill2_i32, dim3(fb), dim3(256), 0, st, S.ccount, nfill, zero, zero_words);
+    const int ab = (int)std::min<int64_t>(std::max<int64_t>((n + 255) / 256, 1), 8192);
+    if (n > 0)
+      hipLaunchKernelGGL(k_assign, dim3(ab, 1), dim3(256), 0, st, d_pts, d_geom, S.ccount, S.cid,
+                         S.rank, d_err);
+    const unsigned sc = (unsigned)scan_tiles(ncell);
+    if (sc > 1)   // a single tile needs no tile totals
+      hipLaunchKernelGGL(k_scan_sums, dim3(sc), dim3(256), 0, st, S.ccount, d_seg_cells, 1, S.tsum);
+    hipLaunchKernelGGL(k_scan_apply, dim3(sc), dim3(256), 0, st, S.ccount, S.cstart, d_seg_cells, 1,
+                       S.tsum);
+    if (n > 0)
+      hipLaunchKernelGGL(k_group, dim3(ab, 1), dim3(256), 0, st, d_pts, d_geom, S.cstart, S.cid,
+                         S.rank, S.grp);
+  }
   const int64_t nwin = (n + kSortWin - 1) / kSortWin;
   const int cb = (int)std::min<int64_t>(std::max<int64_t>((nwin + 3) / 4, 1), 16384);
   if (n > 0)
@@ -1209,6 +1236,8 @@ static int run(const Call &c, uint64_t *npairs, double *wsum, double *ravg) {
   hs.pts[1] = pd[1];
   hs.seg[0] = {0, 0, ncell, 0, kCountStride};
   hs.seg[1] = {0, 0, ncol, 0, 1};
+  hs.seg[2] = {0, 0, ncol * col_blocks(p1.n), 0, 1};
+  hs.seg[3] = {0, 0, ncol * col_blocks(p2.n), 0, 1};
   hs.win_prefix[0][0] = 0;
   hs.win_prefix[0][1] = (p1.n + kSortWin - 1) / kSortWin;
   hs.win_prefix[1][0] = 0;
@@ -1244,12 +1273,13 @@ static int run(const Call &c, uint64_t *npairs, double *wsum, double *ravg) {
   // and 0.0)
   const int64_t words = (int64_t)(((char *)(d_err + 1) - (char *)d_hist) / 4);
   rc = launch_build(st, &d_sm->pts[0], &d_sm->geom[0], S1, p1.n, ncell, ncol, c.mode,
-                    &d_sm->seg[0], &d_sm->seg[1], d_sm->win_prefix[0], d_sm->col_prefix,
+                    &d_sm->seg[0], &d_sm->seg[1], &d_sm->seg[2], d_sm->win_prefix[0], d_sm->col_prefix,
                     d_sm->maxspan, d_err, true, (int *)d_hist, words);
   if (rc) return rc;
   if (!autoc) {
     rc = launch_build(st, &d_sm->pts[1], &d_sm->geom[1], S2, p2.n, ncell, ncol, c.mode,
-                      &d_sm->seg[0], &d_sm->seg[1], d_sm->win_prefix[1], d_sm->col_prefix,
+                      &d_sm->seg[0], &d_sm->seg[1], &d_sm->seg[3], d_sm->win_prefix[1],
+                      d_sm->col_prefix,
                       d_sm->maxspan, d_err, false);
     if (rc) return rc;
   }

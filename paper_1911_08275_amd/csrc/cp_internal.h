@@ -16,6 +16,13 @@ constexpr int kMaxBins = 60;        // separation bins; slots 0 and nb+1 are tra
 constexpr int kMaxPiBins = 256;
 constexpr int kZSortMax = 4096;   // cells up to this many points are z-sorted
 constexpr int kSortWin = 128;     // grouped positions per wave of the z-order pass
+constexpr int kColLds = 8192;     // columns up to which the build groups points through LDS
+constexpr int kColBlocks = 256;   // most blocks of that grouping (matrix of kColBlocks x columns)
+// Blocks of the LDS column grouping for n points: chunks of at least 2048.
+__host__ __device__ inline int col_blocks(int64_t n) {
+  const int64_t b = (n + 2047) / 2048;
+  return (int)(b < 1 ? 1 : (b > kColBlocks ? kColBlocks : b));
+}
 // Work queues of the pair kernel: one per XCD (workgroups are dealt to the
 // MI355X's 8 XCDs round-robin, so blockIdx.x % 8 names the XCD), each
 // holding a contiguous, hence spatially compact, share of the items; a wave

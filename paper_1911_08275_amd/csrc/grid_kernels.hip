@@ -255,6 +255,125 @@ __global__ __launch_bounds__(256) void k_assign(const PointsDev *pts, const Grid
   if (bad) atomicOr(err, bad);
 }
 
+// ------------------------------------------------- column grouping (LDS)
+//
+// The same grouping without any device-scope atomic, when a block's LDS
+// holds one counter per (x, y) column.  Each of nb blocks takes a contiguous
+// chunk of its catalogue's points; pass 1 counts the chunk per column in LDS
+// and writes the counts to a column-major matrix M[col * nb + block]; the
+// exclusive scan of M gives, for every (column, block), where that block's
+// points of that column start in column order (so M'[col * nb] is the
+// column's start and the scan's total its end); pass 2 ranks each block's
+// points inside their column with LDS atomics and writes them in column
+// order; pass 3, one workgroup per column, counts the column's points per
+// z-cell in LDS, writes the cell starts and moves the points to their cells.
+// Order inside a cell is arbitrary, as with k_assign.
+
+__device__ inline int column_of(const GridGeom &G, double x, double y) {
+  return cell_coord(G, 0, x) * G.n[1] + cell_coord(G, 1, y);
+}
+
+// Chunk of a catalogue's points taken by block b of nb.
+__device__ inline void block_chunk(int64_t n, int b, int nb, int64_t &i0, int64_t &i1) {
+  const int64_t per = (n + nb - 1) / nb;
+  i0 = min(n, (int64_t)b * per);
+  i1 = min(n, i0 + per);
+}
+
+// Pass 1 (validates the points as k_assign does); one catalogue.
+__global__ __launch_bounds__(1024) void k_colcount(const PointsDev *pts, const GridGeom *geom,
+                                                   int *mat, int *err) {
+  __shared__ int h[kColLds];
+  const PointsDev P = *pts;
+  const GridGeom &G = *geom;
+  const int ncol = G.n[0] * G.n[1], nb = gridDim.x;
+  for (int c = threadIdx.x; c < ncol; c += blockDim.x) h[c] = 0;
+  __syncthreads();
+  int64_t i0, i1;
+  block_chunk(P.n, blockIdx.x, nb, i0, i1);
+  int bad = 0;
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+    const double v[3] = {load_coord(P.x, P.dtype, i), load_coord(P.y, P.dtype, i),
+                         load_coord(P.z, P.dtype, i)};
+    for (int a = 0; a < 3; a++) {
+      if (!isfinite(v[a])) bad |= ERRF_NONFINITE;
+      else if (G.periodic && (v[a] < 0.0 || v[a] >= G.box)) bad |= ERRF_OUT_OF_BOX;
+    }
+    if (P.w && !isfinite(P.w[i])) bad |= ERRF_NONFINITE;
+    atomicAdd(&h[column_of(G, v[0], v[1])], 1);
+  }
+  if (bad) atomicOr(err, bad);
+  __syncthreads();
+  for (int c = threadIdx.x; c < ncol; c += blockDim.x) mat[(int64_t)c * nb + blockIdx.x] = h[c];
+}
+
+// Pass 2: off = the scanned matrix; out: (x, y, z, w) in column order.
+__global__ __launch_bounds__(1024) void k_colscatter(const PointsDev *pts, const GridGeom *geom,
+                                                     const int *off, double4 *out) {
+  __shared__ int base[kColLds];
+  const PointsDev P = *pts;
+  const GridGeom &G = *geom;
+  const int ncol = G.n[0] * G.n[1], nb = gridDim.x;
+  for (int c = threadIdx.x; c < ncol; c += blockDim.x) base[c] = off[(int64_t)c * nb + blockIdx.x];
+  __syncthreads();
+  int64_t i0, i1;
+  block_chunk(P.n, blockIdx.x, nb, i0, i1);
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+    const double x = load_coord(P.x, P.dtype, i), y = load_coord(P.y, P.dtype, i);
+    const int k = atomicAdd(&base[column_of(G, x, y)], 1);
+    out[G.pbase + k] = make_double4(x, y, load_coord(P.z, P.dtype, i), P.w ? P.w[i] : 1.0);
+  }
+}
+
+// Pass 3: one workgroup per column (blockIdx.x, strided); column col spans
+// [off[col * stride], off[(col + 1) * stride]) of colgrp; grp in cell order,
+// cell starts into cstart.
+__global__ __launch_bounds__(256) void k_colcells(const GridGeom *geom, const int *off,
+                                                  int stride, const double4 *colgrp,
+                                                  double4 *grp, int *cstart) {
+  __shared__ int cnt[kMaxAxisCells + 1];
+  __shared__ int zs[kMaxAxisCells + 1];
+  const GridGeom &G = *geom;
+  const int ncol = G.n[0] * G.n[1], nz = G.n[2];
+  const int tid = threadIdx.x, lane = tid & 63;
+  for (int col = blockIdx.x; col < ncol; col += gridDim.x) {
+    const int c0 = off[(int64_t)col * stride], c1 = off[(int64_t)(col + 1) * stride];
+    for (int z = tid; z <= nz; z += blockDim.x) cnt[z] = 0;
+    __syncthreads();
+    for (int i = c0 + tid; i < c1; i += blockDim.x)
+      atomicAdd(&cnt[cell_coord(G, 2, colgrp[G.pbase + i].z)], 1);
+    __syncthreads();
+    // exclusive scan of the nz counts by wave 0, 64 at a time
+    if (tid < 64) {
+      int carry = 0;
+      for (int z0 = 0; z0 < nz; z0 += 64) {
+        const int v = z0 + lane < nz ? cnt[z0 + lane] : 0;
+        int x = v;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+          const int y = __shfl_up(x, d);
+          if (lane >= d) x += y;
+        }
+        if (z0 + lane < nz) zs[z0 + lane] = carry + x - v;
+        carry += __shfl(x, 63);
+      }
+    }
+    __syncthreads();
+    for (int z = tid; z < nz; z += blockDim.x) {
+      cstart[G.sbase + (int64_t)col * nz + z] = c0 + zs[z];
+      cnt[z] = 0;
+    }
+    if (col == ncol - 1 && tid == 0) cstart[G.sbase + (int64_t)ncol * nz] = c1;
+    __syncthreads();
+    for (int i = c0 + tid; i < c1; i += blockDim.x) {
+      const double4 v = colgrp[G.pbase + i];
+      const int z = cell_coord(G, 2, v.z);
+      grp[G.pbase + c0 + zs[z] + atomicAdd(&cnt[z], 1)] = v;
+    }
+    __syncthreads();
+  }
+}
+
 // Cell order, z ascending inside each cell (Section 2.1 contiguous per-cell
 // storage and z-sorted cells, used by the late entry / early exit of Section
 // 2.2).  k_group copies every point's (x, y, z, w) to its cell's range in the

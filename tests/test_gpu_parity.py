@@ -413,6 +413,36 @@ def test_dense_cell_sorted_path(native, prec):
         _check(g, refw, prec=prec)
 
 
+def test_build_paths_agree(native, monkeypatch):
+    """The two ways of grouping points by cell -- LDS column histograms (grids
+    of up to 8192 columns) and one device-scope atomic per point (any grid) --
+    give the same counts and weighted sums, for auto and cross counts,
+    periodic and not, xi and w_p, float64 and float32 inputs."""
+    cat = synth.clustered(40_000, 800, 1.5, 420.0, seed=12, weights=True)
+    rnd = synth.to_float32(synth.uniform(30_000, 420.0, seed=13, weights=True))
+    edges = synth.log_edges(0.1, 25.0, 14)
+    d, r = native.to_device(cat), native.to_device(rnd)
+    out = {}
+    for path in ("1", "0"):
+        monkeypatch.setenv("CP_BUILD_COLUMNS", path)
+        _say("build path", path)
+        res = [native.countpairs_xi(d, edges, precision="fp32", periodic=True, boxsize=420.0,
+                                    need_ravg=True, refine=(2, 2, 2)),
+               native.countpairs_wp(d, edges, 40.0, 40, precision="fp32", periodic=True,
+                                    boxsize=420.0, refine=(2, 2, 1)),
+               native.countpairs_xi(d, edges, precision="fp64", periodic=False, refine=(2, 2, 2)),
+               native.countpairs_cross(d, r, edges, precision="fp32", periodic=False,
+                                       need_ravg=True, refine=(2, 2, 2))]
+        out[path] = res
+    for a, b in zip(out["1"], out["0"]):
+        assert (a.npairs == b.npairs).all()
+        if a.wsum is not None:
+            np.testing.assert_allclose(a.wsum, b.wsum, rtol=1e-12, atol=0)
+            np.testing.assert_allclose(a.ravg, b.ravg, rtol=1e-12, atol=0)
+    ref = oracle.xi(cat, edges, periodic=False, other=rnd)
+    _check(out["1"][3], ref, weighted=True, prec="fp32", periodic=False)
+
+
 def test_unique_mode_and_pruning_stats(native):
     cat = synth.clustered(30_000, 600, 1.5, 420.0, seed=6)
     edges = synth.log_edges(0.1, 25.0, 14)
