@@ -172,11 +172,36 @@ __device__ inline void add_w(double *p, double w, double wr) {
   atomicAdd(p + 1, wr);
 }
 
+// LDS byte address of a pointer into the workgroup's LDS, and back.
+typedef __attribute__((address_space(3))) uint32_t lds_u32;
+__device__ inline uint32_t lds_addr(uint32_t *p) {
+  return (uint32_t)(uintptr_t)(lds_u32 *)p;
+}
+__device__ inline uint32_t *lds_ptr(uint32_t a) { return (uint32_t *)(lds_u32 *)(uintptr_t)a; }
+
 struct WaveArea {
   uint32_t *hist;
   uint32_t *histx;  // WPXI: the xi counters, one row of slots per lane pair (lane mod 32)
   double *hw;   // weight sums, interleaved: hw[2 i] = sum w, hw[2 i + 1] = sum w r
   uint32_t *list;   // weighted xi, binary32 mode: (tile lane, record) pairs to evaluate
+};
+
+// Address of the (r_p, pi) counter of slot s = t - 1 and pi bin l in a
+// wave's histogram, word (s * npi + l) * wpc + base (wpc copies, interleaved;
+// wpc a power of two): the table entry carries t = s + 1 in its low bits, so
+// the -1 is folded into the lane's base address, and the address takes one
+// 24-bit multiply-add and one shift-add.
+struct WpIndex {
+  uint32_t row4, hb;
+  int lsh;
+  __device__ WpIndex(uint32_t *hist, int npi, int wpc, int base) {
+    row4 = (uint32_t)in_vgpr(npi * wpc * 4);
+    lsh = in_vgpr(wpc == 2 ? 3 : (wpc == 4 ? 4 : (wpc == 8 ? 5 : 2)));
+    hb = lds_addr(hist) + 4u * (uint32_t)base - row4;
+  }
+  __device__ uint32_t *at(uint32_t t, int l) const {
+    return lds_ptr(__umul24(t, row4) + ((uint32_t)l << lsh) + hb);
+  }
 };
 
 // xi counters rows[s * 32 + c] of slots s = 0 .. nb + 1, one column per
@@ -603,12 +628,12 @@ __device__ inline void loop_wp_f32(const PairParams &P, WaveArea A, const LanePt
                                    const uint2 *tab32, const double *sE, uint32_t &nrechk) {
   const int npi = in_vgpr(P.npi), wpc = in_vgpr(P.wpc), lo = in_vgpr(P.tab32_lo);
   const int sh = in_vgpr(P.tab_shift);
-  const int row = npi * wpc;                       // histogram words per slot
   const int base = lane & (wpc - 1);
   const uint2 *tb = tab32 - P.tab32_lo;
   const float AB = in_vgpr(P.AB32), phi = in_vgpr(P.pi_hi32), plo = in_vgpr(P.pi_lo32);
   const float inv = in_vgpr(P.inv_dpi32);
   const float pd = in_vgpr(P.pi_delta), pd1 = in_vgpr(1.0f - P.pi_delta);
+  const WpIndex H(A.hist, npi, wpc, base);
   uint32_t nunc = 0;
   stream_f32(U.strm, U.jb, U.je, [&](int j, float qx, float qy, float qz, float qw) {
     const float v = __builtin_fmaf(ry, qy, __builtin_fmaf(rx, qx, ra)) + qw;
@@ -618,18 +643,14 @@ __device__ inline void loop_wp_f32(const PairParams &P, WaveArea A, const LanePt
     if (pre) {
       const uint2 e = tb[max(__float_as_int(v) >> sh, lo)];
       const float f = pz * inv;
-      const float fl = floorf(f);
-      const float fr = f - fl;
+      const float fr = __builtin_amdgcn_fractf(f);   // f - floor(f), exact for f >= 0
       const bool ch = v >= __uint_as_float(e.y);
       const bool unc = (v >= __uint_as_float(e.x) && !ch) || fr < pd || fr > pd1 || pz >= plo;
       if (unc) {
         recheck_wp<SHIFT>(P, A, L, U, j, sE, base);
         nunc++;
       } else {
-        const int slot = (int)(e.y & 63u) - 1 + (ch ? 1 : 0);
-        const int l = min((int)fl, npi - 1);
-        // 24-bit products (full rate; the 32-bit multiply is quarter rate)
-        atomicAdd(&A.hist[__umul24(slot, row) + __umul24(l, wpc) + base], 1u);
+        atomicAdd(H.at((e.y & 63u) + (ch ? 1u : 0u), min((int)f, npi - 1)), 1u);
       }
     }
   });
@@ -648,7 +669,6 @@ __device__ inline void loop_wpxi_f32(const PairParams &P, WaveArea A, const Lane
                                      const double *sEx, uint32_t &nrechk) {
   const int npi = in_vgpr(P.npi), wpc = in_vgpr(P.wpc), lo = in_vgpr(P.tab32_lo);
   const int sh = in_vgpr(P.tab_shift);
-  const int row = npi * wpc;
   const int base = lane & (wpc - 1);
   const uint2 *tb = tab32 - P.tab32_lo;
   const float AB = in_vgpr(P.AB32), phi = in_vgpr(P.pi_hi32), plo = in_vgpr(P.pi_lo32);
@@ -657,7 +677,9 @@ __device__ inline void loop_wpxi_f32(const PairParams &P, WaveArea A, const Lane
   const int lox = in_vgpr(P.tabx_lo), shx = in_vgpr(P.tabx_shift), nbx = P.nbx;
   const uint2 *tbx = tabx - P.tabx_lo;
   const float ABx = in_vgpr(P.AB32x);
-  const int xc = lane & 31;
+  const WpIndex H(A.hist, npi, wpc, base);
+  // xi counter of slot s at row s, column lane mod 32: byte address (s + 1) * 128 + hx
+  const uint32_t hx = lds_addr(A.histx) + 4u * (uint32_t)(lane & 31) - 128u;
   uint32_t nunc = 0;
   stream_f32(U.strm, U.jb, U.je, [&](int j, float qx, float qy, float qz, float qw) {
     const float v = __builtin_fmaf(ry, qy, __builtin_fmaf(rx, qx, ra)) + qw;
@@ -666,24 +688,21 @@ __device__ inline void loop_wpxi_f32(const PairParams &P, WaveArea A, const Lane
     if (ok && v < AB && pz < phi) {
       const uint2 e = tb[max(__float_as_int(v) >> sh, lo)];
       const float f = pz * inv;
-      const float fl = floorf(f);
-      const float fr = f - fl;
+      const float fr = __builtin_amdgcn_fractf(f);   // f - floor(f), exact for f >= 0
       const bool ch = v >= __uint_as_float(e.y);
       const bool unc = (v >= __uint_as_float(e.x) && !ch) || fr < pd || fr > pd1 || pz >= plo;
       if (unc) {
         recheck_wp<true>(P, A, L, U, j, sE, base);
         nunc++;
       } else {
-        const int slot = (int)(e.y & 63u) - 1 + (ch ? 1 : 0);
-        const int l = min((int)fl, npi - 1);
-        atomicAdd(&A.hist[__umul24(slot, row) + __umul24(l, wpc) + base], 1u);
+        atomicAdd(H.at((e.y & 63u) + (ch ? 1u : 0u), min((int)f, npi - 1)), 1u);
       }
     }
     const float sx = __builtin_fmaf(pz, pz, v);
     if (ok && sx < ABx) {
       const uint2 e = tbx[max(__float_as_int(sx) >> shx, lox)];
       const bool ch = sx >= __uint_as_float(e.y);
-      int slot;
+      uint32_t sl;   // slot + 1
       if (sx >= __uint_as_float(e.x) && !ch) {
         // binary64 re-evaluation (the reference separation)
         sdouble *DP = (sdouble *)U.pos;
@@ -691,12 +710,12 @@ __device__ inline void loop_wpxi_f32(const PairParams &P, WaveArea A, const Lane
         double dx, dy, dz;
         ref_sep<true, false>(L.x, L.y, L.z, DP[4 * j], DP[4 * j + 1], DP[4 * j + 2], U.S, wz, 0.0,
                              0.0, dx, dy, dz);
-        slot = exact_slot(sEx, nbx, (dx * dx + dy * dy) + dz * dz);
+        sl = (uint32_t)exact_slot(sEx, nbx, (dx * dx + dy * dy) + dz * dz) + 1u;
         nunc++;
       } else {
-        slot = (int)(e.y & 63u) - 1 + (ch ? 1 : 0);
+        sl = (e.y & 63u) + (ch ? 1u : 0u);
       }
-      atomicAdd(&A.histx[slot * 32 + xc], 1u);
+      atomicAdd(lds_ptr((sl << 7) + hx), 1u);
     }
   });
   nrechk += nunc;
