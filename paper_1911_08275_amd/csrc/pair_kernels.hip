@@ -186,21 +186,37 @@ struct WaveArea {
   uint32_t *list;   // weighted xi, binary32 mode: (tile lane, record) pairs to evaluate
 };
 
-// Address of the (r_p, pi) counter of slot s = t - 1 and pi bin l in a
-// wave's histogram, word (s * npi + l) * wpc + base (wpc copies, interleaved;
-// wpc a power of two): the table entry carries t = s + 1 in its low bits, so
-// the -1 is folded into the lane's base address, and the address takes one
-// 24-bit multiply-add and one shift-add.
+// a * b + c on the low 24 bits of a and b, and (a << s) + c, one
+// instruction each (the compiler otherwise forms a multiply, a shift and a
+// three-way add).
+__device__ inline uint32_t mad_u24(uint32_t a, uint32_t b, uint32_t c) {
+  uint32_t r;
+  asm("v_mad_u32_u24 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+  return r;
+}
+__device__ inline uint32_t lshl_add(uint32_t a, uint32_t s, uint32_t c) {
+  uint32_t r;
+  asm("v_lshl_add_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(s), "v"(c));
+  return r;
+}
+
+// Address of the (r_p, pi) counter of slot s and pi bin l in a wave's
+// histogram, word (s * npi + l) * wpc + base (wpc copies, interleaved; wpc a
+// power of two).  The table entry's low bits carry t = s + 1 - ch, where ch
+// says the value lies above the entry's upper threshold: the -1 is folded
+// into the lane's base address and ch picks the base one row up, so the
+// address is a select, a 24-bit multiply-add and a shift-add.
 struct WpIndex {
-  uint32_t row4, hb;
-  int lsh;
+  uint32_t row4, hb, hb1;
+  uint32_t lsh;
   __device__ WpIndex(uint32_t *hist, int npi, int wpc, int base) {
     row4 = (uint32_t)in_vgpr(npi * wpc * 4);
-    lsh = in_vgpr(wpc == 2 ? 3 : (wpc == 4 ? 4 : (wpc == 8 ? 5 : 2)));
+    lsh = (uint32_t)in_vgpr(wpc == 2 ? 3 : (wpc == 4 ? 4 : (wpc == 8 ? 5 : 2)));
     hb = lds_addr(hist) + 4u * (uint32_t)base - row4;
+    hb1 = hb + row4;
   }
-  __device__ uint32_t *at(uint32_t t, int l) const {
-    return lds_ptr(__umul24(t, row4) + ((uint32_t)l << lsh) + hb);
+  __device__ uint32_t *at(uint32_t t, bool ch, int l) const {
+    return lds_ptr(lshl_add((uint32_t)l, lsh, mad_u24(t, row4, ch ? hb1 : hb)));
   }
 };
 
@@ -650,7 +666,7 @@ __device__ inline void loop_wp_f32(const PairParams &P, WaveArea A, const LanePt
         recheck_wp<SHIFT>(P, A, L, U, j, sE, base);
         nunc++;
       } else {
-        atomicAdd(H.at((e.y & 63u) + (ch ? 1u : 0u), min((int)f, npi - 1)), 1u);
+        atomicAdd(H.at(e.y & 63u, ch, min((int)f, npi - 1)), 1u);
       }
     }
   });
@@ -679,7 +695,7 @@ __device__ inline void loop_wpxi_f32(const PairParams &P, WaveArea A, const Lane
   const float ABx = in_vgpr(P.AB32x);
   const WpIndex H(A.hist, npi, wpc, base);
   // xi counter of slot s at row s, column lane mod 32: byte address (s + 1) * 128 + hx
-  const uint32_t hx = lds_addr(A.histx) + 4u * (uint32_t)(lane & 31) - 128u;
+  const uint32_t hx = lds_addr(A.histx) + 4u * (uint32_t)(lane & 31) - 128u, hx1 = hx + 128u;
   uint32_t nunc = 0;
   stream_f32(U.strm, U.jb, U.je, [&](int j, float qx, float qy, float qz, float qw) {
     const float v = __builtin_fmaf(ry, qy, __builtin_fmaf(rx, qx, ra)) + qw;
@@ -695,14 +711,14 @@ __device__ inline void loop_wpxi_f32(const PairParams &P, WaveArea A, const Lane
         recheck_wp<true>(P, A, L, U, j, sE, base);
         nunc++;
       } else {
-        atomicAdd(H.at((e.y & 63u) + (ch ? 1u : 0u), min((int)f, npi - 1)), 1u);
+        atomicAdd(H.at(e.y & 63u, ch, min((int)f, npi - 1)), 1u);
       }
     }
     const float sx = __builtin_fmaf(pz, pz, v);
     if (ok && sx < ABx) {
       const uint2 e = tbx[max(__float_as_int(sx) >> shx, lox)];
       const bool ch = sx >= __uint_as_float(e.y);
-      uint32_t sl;   // slot + 1
+      uint32_t ad;
       if (sx >= __uint_as_float(e.x) && !ch) {
         // binary64 re-evaluation (the reference separation)
         sdouble *DP = (sdouble *)U.pos;
@@ -710,12 +726,12 @@ __device__ inline void loop_wpxi_f32(const PairParams &P, WaveArea A, const Lane
         double dx, dy, dz;
         ref_sep<true, false>(L.x, L.y, L.z, DP[4 * j], DP[4 * j + 1], DP[4 * j + 2], U.S, wz, 0.0,
                              0.0, dx, dy, dz);
-        sl = (uint32_t)exact_slot(sEx, nbx, (dx * dx + dy * dy) + dz * dz) + 1u;
+        ad = ((uint32_t)exact_slot(sEx, nbx, (dx * dx + dy * dy) + dz * dz) << 7) + hx1;
         nunc++;
       } else {
-        sl = (e.y & 63u) + (ch ? 1u : 0u);
+        ad = lshl_add(e.y & 63u, 7u, ch ? hx1 : hx);
       }
-      atomicAdd(lds_ptr((sl << 7) + hx), 1u);
+      atomicAdd(lds_ptr(ad), 1u);
     }
   });
   nrechk += nunc;
