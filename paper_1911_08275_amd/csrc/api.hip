@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <functional>
 #include <cfloat>
 #include <cmath>
 #include <cstdio>
@@ -937,8 +938,43 @@ static std::string tune_key(const Call &c, double volume) {
 
 static int run(const Call &c, uint64_t *npairs, double *wsum, double *ravg);
 
-// Times the candidates on every call of `calls` (the objective is their sum)
-// and stores the best settings under key.
+// Device time of one candidate's settings (refine, chunk target, waves).
+using TuneTimer = std::function<int(const int ref[3], int chunk, int waves, double &ms)>;
+
+// Coordinate descent over the candidates with `time_of` as the objective;
+// stores the best settings under key.
+static int tune_with(const TuneTimer &time_of, const std::string &key, TuneChoice &best) {
+  best = TuneChoice();
+  best.ms = INFINITY;
+  // a candidate that does not fit a caller's workspace is skipped
+  auto consider = [&](const int ref[3], int chunk, int waves) -> int {
+    double ms;
+    const int rc = time_of(ref, chunk, waves, ms);
+    if (rc == CP_ERR_NOMEM) return CP_OK;
+    if (rc) return rc;
+    if (ms < best.ms) {
+      for (int a = 0; a < 3; a++) best.refine[a] = ref[a];
+      best.chunk_pct = chunk;
+      best.waves = waves;
+      best.ms = ms;
+    }
+    return CP_OK;
+  };
+  int rc;
+  for (const auto &ref : kRefineCands)
+    if ((rc = consider(ref, 100, 4))) return rc;
+  if (!std::isfinite(best.ms)) return fail(CP_ERR_NOMEM, "no tuning candidate fits the workspace");
+  const int bref[3] = {best.refine[0], best.refine[1], best.refine[2]};
+  for (int ch : kChunkCands)
+    if ((rc = consider(bref, ch, 4))) return rc;
+  const int bch = best.chunk_pct;
+  for (int wv : kWaveCands)
+    if ((rc = consider(bref, bch, wv))) return rc;
+  tune_store(key, best);
+  return CP_OK;
+}
+
+// Times the candidates on every call of `calls` (the objective is their sum).
 static int tune(const std::vector<Call> &calls, const std::string &key, TuneChoice &best) {
   std::vector<cp_options> opts;
   for (const Call &c : calls) opts.push_back(*c.o);
@@ -968,34 +1004,7 @@ static int tune(const std::vector<Call> &calls, const std::string &key, TuneChoi
     }
     return CP_OK;
   };
-  best = TuneChoice();
-  best.ms = INFINITY;
-  // a candidate that does not fit a caller's workspace is skipped
-  auto consider = [&](const int ref[3], int chunk, int waves) -> int {
-    double ms;
-    const int rc = time_of(ref, chunk, waves, ms);
-    if (rc == CP_ERR_NOMEM) return CP_OK;
-    if (rc) return rc;
-    if (ms < best.ms) {
-      for (int a = 0; a < 3; a++) best.refine[a] = ref[a];
-      best.chunk_pct = chunk;
-      best.waves = waves;
-      best.ms = ms;
-    }
-    return CP_OK;
-  };
-  int rc;
-  for (const auto &ref : kRefineCands)
-    if ((rc = consider(ref, 100, 4))) return rc;
-  if (!std::isfinite(best.ms)) return fail(CP_ERR_NOMEM, "no tuning candidate fits the workspace");
-  const int bref[3] = {best.refine[0], best.refine[1], best.refine[2]};
-  for (int ch : kChunkCands)
-    if ((rc = consider(bref, ch, 4))) return rc;
-  const int bch = best.chunk_pct;
-  for (int wv : kWaveCands)
-    if ((rc = consider(bref, bch, wv))) return rc;
-  tune_store(key, best);
-  return CP_OK;
+  return tune_with(time_of, key, best);
 }
 
 // ------------------------------------------------------------- single call
@@ -1881,9 +1890,11 @@ int cp_plan_destroy(cp_plan *pl) {
   return CP_OK;
 }
 
-int cp_plan_create(const cp_points *mocks, int nmocks, const double *xi_edges, int xi_nedges,
-                   const double *wp_edges, int wp_nedges, double pimax, int npibins,
-                   const cp_options *o, cp_plan **out) {
+// forced: launch settings to use as given (the tuner's trial plans), else
+// the caller's refine or the tuned settings.
+static int plan_create(const cp_points *mocks, int nmocks, const double *xi_edges, int xi_nedges,
+                       const double *wp_edges, int wp_nedges, double pimax, int npibins,
+                       const cp_options *o, const TuneChoice *forced, cp_plan **out) {
   try {
     if (!out) return fail(CP_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
@@ -1929,26 +1940,73 @@ int cp_plan_create(const cp_points *mocks, int nmocks, const double *xi_edges, i
       pl->pts.push_back(d);
     }
     const int prec = o->precision == CP_PREC_FP32_RECHECK ? F32R : F64;
-    // launch settings: the caller's refine, or tuned on the median catalogue
-    // by timing single calls of the requested statistics (cached)
+    // xi and w_p in one launch (binary32): every xi pair must lie in the w_p
+    // search (xi R_max at most r_p,max and pi_max); CP_PLAN_FUSED=0 keeps two
+    const char *fe = getenv("CP_PLAN_FUSED");
+    const bool want_fused = xi_edges && wp_edges && prec == F32R && !(fe && fe[0] == '0') &&
+                            xi_edges[xi_nedges - 1] <= wp_edges[wp_nedges - 1] &&
+                            xi_edges[xi_nedges - 1] <= pimax;
+    // launch settings: the caller's refine, or tuned (cached): by timing
+    // single calls of the requested statistics on the median catalogue, or,
+    // for a fused launch, plans of up to four catalogues picked at even
+    // quantiles of the pair work (taken as n^2), which the largest dominate
     cp_options po = *o;
     po.need_ravg = 0;
     po.count_mode = CP_ORDERED;
     TuneChoice tc;
-    if (!po.refine[0] && !po.refine[1] && !po.refine[2]) {
+    if (forced) {
+      tc = *forced;
+      for (int a = 0; a < 3; a++) po.refine[a] = tc.refine[a];
+      pl->tuned = 0;
+    } else if (!po.refine[0] && !po.refine[1] && !po.refine[2]) {
       pl->tuned = 3;
       if (autotune_on()) {
         const int med = pl->order[nmocks / 2];   // order: decreasing size
         std::vector<Call> calls;
-        if (xi_edges) calls.push_back(Call{XI, false, &mocks[med], nullptr, xi_edges, xi_nedges, 0.0, 1, &po});
+        if (xi_edges && !want_fused)
+          calls.push_back(Call{XI, false, &mocks[med], nullptr, xi_edges, xi_nedges, 0.0, 1, &po});
         if (wp_edges)
           calls.push_back(Call{WP, false, &mocks[med], nullptr, wp_edges, wp_nedges, pimax, npibins, &po});
         const double vol = po.boxsize * po.boxsize * po.boxsize;
-        const std::string key = "plan:" + tune_key(calls[0], vol) + (calls.size() > 1 ? "+wp" : "");
+        const std::string key = "plan:" + tune_key(calls[0], vol) +
+                                (want_fused ? "+fused" : calls.size() > 1 ? "+wp" : "");
         if (tune_lookup(key, tc)) {
           pl->tuned = 2;
         } else {
-          if ((rc = tune(calls, key, tc))) {
+          if (want_fused) {
+            std::vector<cp_points> trial;
+            double tot = 0.0, acc = 0.0;
+            for (int q = 0; q < nmocks; q++) tot += (double)pl->n[q] * (double)pl->n[q];
+            const int K = std::min(nmocks, 4);
+            for (int q = 0, k = 0; q < nmocks && k < K; q++) {
+              acc += (double)pl->n[q] * (double)pl->n[q];
+              // catalogue q (in decreasing size) holds quantile (k + 1/2) / K
+              for (; k < K && acc >= tot * (k + 0.5) / K; k++) trial.push_back(mocks[pl->order[q]]);
+            }
+            const TuneTimer ptime = [&](const int ref[3], int chunk, int waves, double &ms) -> int {
+              TuneChoice f;
+              for (int a = 0; a < 3; a++) f.refine[a] = ref[a];
+              f.chunk_pct = chunk;
+              f.waves = waves;
+              cp_plan *sp = nullptr;
+              int r = plan_create(trial.data(), (int)trial.size(), xi_edges, xi_nedges, wp_edges,
+                                  wp_nedges, pimax, npibins, o, &f, &sp);
+              if (r) return r;
+              ms = INFINITY;
+              for (int rep = 0; rep < 3 && !r; rep++) {
+                cp_stats xs;
+                if (!(r = cp_plan_execute(sp, o->stream)) && !(r = cp_plan_stats(sp, &xs, nullptr)) &&
+                    rep > 0)
+                  ms = std::min(ms, (double)xs.ms_total);
+              }
+              cp_plan_destroy(sp);
+              return r;
+            };
+            rc = tune_with(ptime, key, tc);
+          } else {
+            rc = tune(calls, key, tc);
+          }
+          if (rc) {
             cp_plan_destroy(pl);
             return rc;
           }
@@ -1970,12 +2028,7 @@ int cp_plan_create(const cp_points *mocks, int nmocks, const double *xi_edges, i
       cp_plan_destroy(pl);
       return rc;
     }
-    // xi and w_p in one launch (binary32): every xi pair must lie in the w_p
-    // search (xi R_max at most r_p,max and pi_max); CP_PLAN_FUSED=0 keeps two
-    const char *fe = getenv("CP_PLAN_FUSED");
-    if (xi_edges && wp_edges && pl->xi.prec == F32R && pl->wp.prec == F32R &&
-        !(fe && fe[0] == '0') && xi_edges[xi_nedges - 1] <= wp_edges[wp_nedges - 1] &&
-        xi_edges[xi_nedges - 1] <= pimax &&
+    if (want_fused && pl->xi.prec == F32R && pl->wp.prec == F32R &&
         make_binning_wpxi(xi_edges, xi_nedges, pl->wp.B, pl->xbin)) {
       Batch &b = pl->wp;
       const int n32 = (int)b.B.t32.e.size(), n64 = (int)b.B.t64.e.size();
@@ -2050,6 +2103,13 @@ int cp_plan_create(const cp_points *mocks, int nmocks, const double *xi_edges, i
   } catch (...) {
     return fail(CP_ERR_INTERNAL, "unexpected exception");
   }
+}
+
+int cp_plan_create(const cp_points *mocks, int nmocks, const double *xi_edges, int xi_nedges,
+                   const double *wp_edges, int wp_nedges, double pimax, int npibins,
+                   const cp_options *o, cp_plan **out) {
+  return plan_create(mocks, nmocks, xi_edges, xi_nedges, wp_edges, wp_nedges, pimax, npibins, o,
+                     nullptr, out);
 }
 
 int cp_plan_execute(cp_plan *pl, void *stream) {
