@@ -742,7 +742,7 @@ struct Binning {
   float AB32;
   float eps32, eps32_3;
   Bounds bnd;
-  float inv_dpi32, pi_delta, pi_lo32, pi_hi32;
+  float inv_dpi32, pi_delta, pi_hi32;
   double dpi;
 };
 
@@ -788,13 +788,17 @@ static int make_binning(int mode, int prec, const double *edges, int nedges, dou
   if (mode == WP) {
     const double u = std::ldexp(1.0, -24);
     B.inv_dpi32 = (float)(1.0 / B.dpi);
-    B.pi_delta = (float)(B.bnd.eta_pi / B.dpi + 3 * u * npi + 1e-12 * npi);
-    B.pi_lo32 = f32_down(pimax - B.bnd.eta_pi);
+    // pi band, in units of dpi: the estimate's error eta_pi, the roundings of
+    // fl32(1 / dpi) and of the product (2u of at most npi + 1), the rounding
+    // of the pre-filter pi_hi32 and of fl32(1 - pi_delta), and the binary64
+    // edges; it also covers pi_max itself, whose edge is the integer npi, so
+    // a pair away from every integer is surely below pi_max
+    B.pi_delta = (float)(B.bnd.eta_pi / B.dpi + 8 * u * npi + 1e-12 * npi);
     B.pi_hi32 = f32_up(pimax + B.bnd.eta_pi);
   } else {
     B.inv_dpi32 = 1.0f;
     B.pi_delta = 0.f;
-    B.pi_lo32 = B.pi_hi32 = 0.f;
+    B.pi_hi32 = 0.f;
   }
   return CP_OK;
 }
@@ -1331,7 +1335,6 @@ static int run(const Call &c, uint64_t *npairs, double *wsum, double *ravg) {
   P.npi = npi;
   P.inv_dpi32 = B.inv_dpi32;
   P.pi_delta = B.pi_delta;
-  P.pi_lo32 = B.pi_lo32;
   P.pi_hi32 = B.pi_hi32;
   P.autocorr = autoc ? 1 : 0;
   P.weighted = weighted ? 1 : 0;
@@ -1805,7 +1808,6 @@ static int batch_upload(cp_plan &pl, Batch &b) {
   P.wpc = b.wpc;
   P.inv_dpi32 = b.B.inv_dpi32;
   P.pi_delta = b.B.pi_delta;
-  P.pi_lo32 = b.B.pi_lo32;
   P.pi_hi32 = b.B.pi_hi32;
   P.autocorr = 1;
   P.weighted = 0;

@@ -163,7 +163,7 @@ struct PairParams {
   double pimax, dpi, inv_dpi;   // inv_dpi = fl(1 / dpi)
   int npi;
   int wpc;                   // copies of the wave's histogram (power of two)
-  float inv_dpi32, pi_delta, pi_lo32, pi_hi32;
+  float inv_dpi32, pi_delta, pi_hi32;
   // flags
   int autocorr;
   int weighted;

@@ -127,6 +127,17 @@ __device__ inline int slot64(const uint2 *tab, int lo, int hi, int sh, const dou
   return h.slot;
 }
 
+// The same for s < E_B: fl32(s) <= fl32(E_B) lies at or below the table's
+// top cell, so the index is clamped below only; tb = the table minus lo.
+__device__ inline int slot64_below(const uint2 *tb, int lo, int sh, const double *E, int nb,
+                                   double s) {
+  const float v = (float)s;
+  const uint2 e = tb[max(__float_as_int(v) >> sh, lo)];
+  const bool ch = v >= __uint_as_float(e.y);
+  if (v >= __uint_as_float(e.x) && !ch) return exact_slot(E, nb, s);
+  return (int)(e.y & 63u) - 1 + (ch ? 1 : 0);
+}
+
 // Square root for the weighted mean separation (not part of any bin
 // decision): the hardware reciprocal square root (relative error ~5e-8 on
 // gfx950) refined by one Newton step in binary64, measured relative error
@@ -616,9 +627,11 @@ __device__ inline void loop_xi_f32(const PairParams &P, WaveArea A, const LanePt
 // sight pi~ = |qz - rz| (cell-local coordinates) is binned by multiplying
 // with 1/dpi, and a pair is in range when v~ < AB32 and pi~ < pi_hi32 (not
 // surely beyond r_p,max or pi_max); it is uncertain when v~ lies in an edge's
-// band, when the fraction of pi~ / dpi lies within pi_delta of a pi edge, or
-// when pi~ >= pi_lo32 (near pi_max).  v~ < AB32 keeps the table index at or
-// below the table's top, so the index is clamped below only.
+// band or when the fraction of f = pi~ / dpi lies within pi_delta of an
+// integer.  pi_max is the edge at the integer npi and the band covers the
+// pre-filter's slack, so a certain pair is below pi_max and its bin floor(f)
+// is at most npi - 1.  v~ < AB32 keeps the table index at or below the
+// table's top, so the index is clamped below only.
 
 // Binary64 re-evaluation of one uncertain wp pair (unweighted).
 template <bool SHIFT>
@@ -646,7 +659,7 @@ __device__ inline void loop_wp_f32(const PairParams &P, WaveArea A, const LanePt
   const int sh = in_vgpr(P.tab_shift);
   const int base = lane & (wpc - 1);
   const uint2 *tb = tab32 - P.tab32_lo;
-  const float AB = in_vgpr(P.AB32), phi = in_vgpr(P.pi_hi32), plo = in_vgpr(P.pi_lo32);
+  const float AB = in_vgpr(P.AB32), phi = in_vgpr(P.pi_hi32);
   const float inv = in_vgpr(P.inv_dpi32);
   const float pd = in_vgpr(P.pi_delta), pd1 = in_vgpr(1.0f - P.pi_delta);
   const WpIndex H(A.hist, npi, wpc, base);
@@ -661,12 +674,12 @@ __device__ inline void loop_wp_f32(const PairParams &P, WaveArea A, const LanePt
       const float f = pz * inv;
       const float fr = __builtin_amdgcn_fractf(f);   // f - floor(f), exact for f >= 0
       const bool ch = v >= __uint_as_float(e.y);
-      const bool unc = (v >= __uint_as_float(e.x) && !ch) || fr < pd || fr > pd1 || pz >= plo;
+      const bool unc = (v >= __uint_as_float(e.x) && !ch) || fr < pd || fr > pd1;
       if (unc) {
         recheck_wp<SHIFT>(P, A, L, U, j, sE, base);
         nunc++;
       } else {
-        atomicAdd(H.at(e.y & 63u, ch, min((int)f, npi - 1)), 1u);
+        atomicAdd(H.at(e.y & 63u, ch, (int)f), 1u);
       }
     }
   });
@@ -687,7 +700,7 @@ __device__ inline void loop_wpxi_f32(const PairParams &P, WaveArea A, const Lane
   const int sh = in_vgpr(P.tab_shift);
   const int base = lane & (wpc - 1);
   const uint2 *tb = tab32 - P.tab32_lo;
-  const float AB = in_vgpr(P.AB32), phi = in_vgpr(P.pi_hi32), plo = in_vgpr(P.pi_lo32);
+  const float AB = in_vgpr(P.AB32), phi = in_vgpr(P.pi_hi32);
   const float inv = in_vgpr(P.inv_dpi32);
   const float pd = in_vgpr(P.pi_delta), pd1 = in_vgpr(1.0f - P.pi_delta);
   const int lox = in_vgpr(P.tabx_lo), shx = in_vgpr(P.tabx_shift), nbx = P.nbx;
@@ -706,12 +719,12 @@ __device__ inline void loop_wpxi_f32(const PairParams &P, WaveArea A, const Lane
       const float f = pz * inv;
       const float fr = __builtin_amdgcn_fractf(f);   // f - floor(f), exact for f >= 0
       const bool ch = v >= __uint_as_float(e.y);
-      const bool unc = (v >= __uint_as_float(e.x) && !ch) || fr < pd || fr > pd1 || pz >= plo;
+      const bool unc = (v >= __uint_as_float(e.x) && !ch) || fr < pd || fr > pd1;
       if (unc) {
         recheck_wp<true>(P, A, L, U, j, sE, base);
         nunc++;
       } else {
-        atomicAdd(H.at(e.y & 63u, ch, min((int)f, npi - 1)), 1u);
+        atomicAdd(H.at(e.y & 63u, ch, (int)f), 1u);
       }
     }
     const float sx = __builtin_fmaf(pz, pz, v);
@@ -747,7 +760,7 @@ __device__ inline void loop_wp_f32_w(const PairParams &P, WaveArea A, const Lane
   const int sh = in_vgpr(P.tab_shift);
   const int row = npi * wpc, cpy = lane & (wpc - 1);
   const uint2 *tb = tab32 - P.tab32_lo;
-  const float AB = in_vgpr(P.AB32), phi = in_vgpr(P.pi_hi32), plo = in_vgpr(P.pi_lo32);
+  const float AB = in_vgpr(P.AB32), phi = in_vgpr(P.pi_hi32);
   const float inv = in_vgpr(P.inv_dpi32);
   const float pd = in_vgpr(P.pi_delta), pd1 = in_vgpr(1.0f - P.pi_delta);
   const int wrapax[3] = {0, 0, 0};
@@ -761,15 +774,13 @@ __device__ inline void loop_wp_f32_w(const PairParams &P, WaveArea A, const Lane
              if (inr) {
                const uint2 e = tb[max(__float_as_int(v) >> sh, lo)];
                const float f = pz * inv;
-               const float fl = floorf(f);
-               const float fr = f - fl;
+               const float fr = __builtin_amdgcn_fractf(f);   // f - floor(f), exact for f >= 0
                const bool ch = v >= __uint_as_float(e.y);
-               const bool unc =
-                   (v >= __uint_as_float(e.x) && !ch) || fr < pd || fr > pd1 || pz >= plo;
+               const bool unc = (v >= __uint_as_float(e.x) && !ch) || fr < pd || fr > pd1;
                double dx, dy, dz;
                ref_sep<SHIFT, false>(L.x, L.y, L.z, ux, uy, uz, U.S, wrapax, 0.0, 0.0, dx, dy,
                                      dz);
-               int sl = (int)(e.y & 63u) - 1 + (ch ? 1 : 0), ll = min((int)fl, npi - 1);
+               int sl = (int)(e.y & 63u) - 1 + (ch ? 1 : 0), ll = (int)f;
                bool keep = true;
                if (unc) {
                  nrechk++;
@@ -1090,7 +1101,8 @@ __device__ inline void loop_f64(const PairParams &P, WaveArea A, const LanePt &L
                                 const Unit &U, const int wrapax[3], double box, double half,
                                 const uint2 *tab64, const double *sE) {
   const double EB = P.EB;
-  const int lo = P.tab64_lo, hi = P.tab64_hi, sh = P.tab_shift;
+  const int lo = P.tab64_lo, sh = P.tab_shift;
+  const uint2 *tb = tab64 - lo;
   const int nb = P.nb, npi = P.npi;
   stream_f64(U.pos, U.jb, U.je, [&](int j, double ux, double uy, double uz, double uw) {
     double dx, dy, dz;
@@ -1101,7 +1113,7 @@ __device__ inline void loop_f64(const PairParams &P, WaveArea A, const LanePt &L
       bool inr = s64 < EB;
       if (OWN) inr = inr && (j > L.iloc);
       if (inr) {
-        const int slot = slot64(tab64, lo, hi, sh, sE, nb, s64);
+        const int slot = slot64_below(tb, lo, sh, sE, nb, s64);
         atomicAdd(&A.hist[slot * 64 + lane], 1u);
         if (W) {
           const double ww = L.w * uw;
@@ -1113,7 +1125,7 @@ __device__ inline void loop_f64(const PairParams &P, WaveArea A, const LanePt &L
       bool inr = (rp2 < EB) && (pz64 < P.pimax);
       if (OWN) inr = inr && (j > L.iloc);
       if (inr) {
-        const int slot = slot64(tab64, lo, hi, sh, sE, nb, rp2);
+        const int slot = slot64_below(tb, lo, sh, sE, nb, rp2);
         const int l = exact_pibin(pz64, P.dpi, P.inv_dpi, npi);
         const int c = (slot * npi + l) * P.wpc + (lane & (P.wpc - 1));
         atomicAdd(&A.hist[c], 1u);

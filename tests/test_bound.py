@@ -192,3 +192,63 @@ def test_pi_bin_without_division():
         l2 = l1 + ((l1 + 1 < npi) & (pz >= lq[np.minimum(l1 + 1, npi)])).astype(np.int64)
         want = np.searchsorted(q[1:npi], pz, side="right")
         assert np.array_equal(l2, want)
+
+
+def _f32_up(x):
+    """Smallest binary32 value >= x (elementwise)."""
+    x = np.asarray(x, dtype=np.float64)
+    r = x.astype(np.float32)
+    return np.where(r.astype(np.float64) < x, np.nextafter(r, np.float32(np.inf)), r)
+
+
+def _f32_down(x):
+    """Largest binary32 value <= x (elementwise)."""
+    x = np.asarray(x, dtype=np.float64)
+    r = x.astype(np.float32)
+    return np.where(r.astype(np.float64) > x, np.nextafter(r, np.float32(-np.inf)), r)
+
+
+def pi_band(eta, dpi, npi):
+    """The binary32 pi band of the w_p loops, in units of dpi."""
+    return np.float32(eta / dpi + 8 * U * npi + 1e-12 * npi)
+
+
+@pytest.mark.parametrize("seed", [41, 42])
+def test_pi_binary32_decision(seed):
+    """Binary32 pi decision of the w_p loops: a pair is counted at once when
+    pi~ < pi_hi32 = up32(pi_max + eta) and the fraction of
+    f = fl32(pi~ * fl32(1 / dpi)) lies in [pi_delta, fl32(1 - pi_delta)]; it
+    goes to bin floor(f).  For every estimate within eta of |dz| that must be
+    the bin of |dz| under the binary64 edges q_l = fl(l dpi), with |dz| below
+    pi_max (the loops keep no separate test near pi_max).  |dz| is placed on
+    and around every edge, pi_max included, with estimates at both ends of
+    its error interval and at the nearest binary32 value."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    counted = 0
+    for _ in range(150):
+        pimax = float(rng.uniform(0.5, 300.0))
+        npi = int(rng.integers(1, 257))
+        dpi = pimax / npi
+        eta = dpi * float(10.0 ** rng.uniform(-9.0, -4.0))
+        inv = np.float32(1.0 / dpi)
+        pd = pi_band(eta, dpi, npi)
+        pd1 = np.float32(np.float32(1.0) - pd)
+        phi = _f32_up(pimax + eta)
+        q = np.array([l * dpi for l in range(1, npi)] + [pimax])
+        base = np.concatenate([q, np.nextafter(q, 0.0), np.nextafter(q, np.inf),
+                               rng.uniform(0.0, 1.02 * pimax, 300)])
+        offs = np.array([-4.0, -2.0, -1.0, -0.6, -0.2, 0.0, 0.2, 0.6, 1.0, 2.0, 4.0]) * eta
+        step = 8 * U * max(npi, 1) * dpi * np.array([-1.0, -0.5, 0.5, 1.0])
+        dz = np.concatenate([(base[:, None] + offs[None, :]).ravel(),
+                             (q[:, None] + step[None, :]).ravel()])
+        dz = dz[dz >= 0.0]
+        truebin = np.searchsorted(q[:-1], dz, side="right")
+        for est in (dz.astype(np.float32), _f32_up(np.maximum(dz - eta, 0.0)), _f32_down(dz + eta)):
+            ok = np.abs(est.astype(np.float64) - dz) <= eta
+            f = est * inv                       # binary32 product
+            fr = f - np.floor(f)                # exact: the kernels' v_fract
+            certain = ok & (est < phi) & (fr >= pd) & (fr <= pd1)
+            counted += int(certain.sum())
+            assert np.all(dz[certain] < pimax)
+            assert np.array_equal(np.floor(f[certain]).astype(np.int64), truebin[certain])
+    assert counted > 10000
