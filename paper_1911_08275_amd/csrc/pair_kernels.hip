@@ -319,6 +319,7 @@ struct LanePt {
   double x, y, z, w;
   int iloc;   // sorted index relative to the catalogue (own-cell ordering)
 };
+constexpr double kNoPoint = 1e200;   // coordinates of the lanes beyond a tile's points
 
 // ------------------------------------------------------------- streaming
 //
@@ -1250,9 +1251,9 @@ void k_pairs(PairParams P) {
     const bool valid = lane < tn;
     const double4 pp = P.pos1[tp0 + (valid ? lane : 0)];
     LanePt L;
-    L.x = valid ? pp.x : 1e200;
-    L.y = valid ? pp.y : 1e200;
-    L.z = valid ? pp.z : 1e200;
+    L.x = valid ? pp.x : kNoPoint;
+    L.y = valid ? pp.y : kNoPoint;
+    L.z = valid ? pp.z : kNoPoint;
     L.w = pp.w;
     L.iloc = (int)(tp0 + lane - G1.pbase);
     // tile bounding box
@@ -1279,6 +1280,7 @@ void k_pairs(PairParams P) {
     for (int base = 0; base < total; base += 64) {
       const int t = base + lane;
       int keep = 0, pruned = 0, cell = 0, packed = 0, slots = 0, win = 0, wzlo = 0, wzhi = 0;
+      int mrg = 0;   // binary64 w_p: may join a run of z-cells (z-sorted, windows computable)
       if (t < total) {
         // column of the tile's list (order fixed by the host's split) and
         // z offset; an auto-count searches its own column forward in z only,
@@ -1370,19 +1372,23 @@ void k_pairs(PairParams P) {
                                 : P.pimax * (1.0 + 1e-9);
                 hz = hz + 1e-9 * (fabs(blz) + fabs(bhz) + fabs(S2) + 1.0);
                 const double zl = blz - S2 - hz, zh = bhz - S2 + hz;
-                if (zl > B.lo[2] || zh < B.hi[2]) {
-                  win = 1;
+                const bool cut = zl > B.lo[2] || zh < B.hi[2];
+                // (w_p: the window depends on the shift only, so the cells
+                // of a run share it; each keeps its bounds)
+                if (cut || (MODE == WP && PREC == F64)) {
                   wzlo = __float_as_int(__double2float_rd(zl));
                   wzhi = __float_as_int(__double2float_ru(zh));
                 }
+                win = cut ? 1 : 0;
+                mrg = MODE == WP && PREC == F64 ? 1 : 0;
               }
             }
           }
         }
         if (ok) {
           // shift code per axis (-1, 0, +1 -> 0, 1, 2) in bits 1..6 of keep,
-          // z-window flag in bit 7
-          keep = 1 | ((sx + 1) << 1) | ((sy + 1) << 3) | ((sz + 1) << 5) | (win << 7);
+          // z-window flag in bit 7, run flag in bit 8
+          keep = 1 | ((sx + 1) << 1) | ((sy + 1) << 3) | ((sz + 1) << 5) | (win << 7) | (mrg << 8);
           packed = X | (Y << 10) | (Z << 20) | (own << 30);
         }
       }
@@ -1395,6 +1401,26 @@ void k_pairs(PairParams P) {
         const int pk = __builtin_amdgcn_readlane(packed, src);
         const int kc = __builtin_amdgcn_readlane(keep, src);
         const int sl = __builtin_amdgcn_readlane(slots, src);
+        // binary64 w_p: the following lanes' cells that continue this column
+        // upwards in z with the same shift and own flag join the unit (cells
+        // are stored z-fastest, so the run's records are contiguous and,
+        // z-sorted per cell, sorted as a whole; the binary64 loops read
+        // absolute positions, while the binary32 records are in each cell's
+        // own frame, which a run would have to switch at every cell)
+        int nrun = 1, winr = kc & 128;
+        if (MODE == WP && PREC == F64 && (kc & 256)) {
+          int last = src, pl = pk;
+          while (last < 63 && ((mk >> (last + 1)) & 1ull)) {
+            const int pk2 = __builtin_amdgcn_readlane(packed, last + 1);
+            const int kc2 = __builtin_amdgcn_readlane(keep, last + 1);
+            if (pk2 != pl + (1 << 20) || ((kc2 ^ kc) & 0x7E) || !(kc2 & 256)) break;
+            last++;
+            mk &= ~(1ull << last);
+            nrun++;
+            pl = pk2;
+            winr |= kc2 & 128;
+          }
+        }
         const int X = pk & 1023, Y = (pk >> 10) & 1023, Z = (pk >> 20) & 1023;
         const bool own = (pk >> 30) & 1;
         const int sxx = ((kc >> 1) & 3) - 1, syy = ((kc >> 3) & 3) - 1, szz = ((kc >> 5) & 3) - 1;
@@ -1407,17 +1433,17 @@ void k_pairs(PairParams P) {
         U.strm = P.strm2 + pbase2;
         U.pos = P.pos2 + pbase2;
         U.jb = CS[G2.sbase + c2];
-        U.je = CS[G2.sbase + c2 + 1];
+        U.je = CS[G2.sbase + c2 + nrun];
         U.slot_lo = sl & 255;
         U.slot_hi = (sl >> 8) & 255;
-        if (kc & 128) {
+        if (winr) {
           const float zlo = __int_as_float(__builtin_amdgcn_readlane(wzlo, src));
           const float zhi = __int_as_float(__builtin_amdgcn_readlane(wzhi, src));
           zwindow(U.pos, zlo, zhi, lane, U.jb, U.je);
           if (U.je <= U.jb) continue;
         }
         const unsigned long long nj = (unsigned long long)(U.je - U.jb);
-        st_cells++;
+        st_cells += (unsigned long long)nrun;
         since_flush += nj;
         if (since_flush > flush_limit) {
           flush_hist<MODE, W>(P, A, cur_mock, lane);
