@@ -604,7 +604,8 @@ __device__ inline void loop_xi_f32(const PairParams &P, WaveArea A, const LanePt
                                    float rx, float ry, float rz, float ra, const Unit &U,
                                    const uint2 *tab32, const double *sE, uint32_t &nrechk) {
   const float AB = P.AB32;
-  const int lo = P.tab32_lo, hi = P.tab32_hi, sh = P.tab_shift;
+  const int lo = P.tab32_lo, sh = P.tab_shift;
+  const uint2 *tb = tab32 - lo;   // s~ < AB32, the table's top: clamped below only
   const int nb = P.nb;
   uint32_t nunc = 0;
   stream_f32(U.strm, U.jb, U.je, [&](int j, float qx, float qy, float qz, float qw) {
@@ -612,7 +613,11 @@ __device__ inline void loop_xi_f32(const PairParams &P, WaveArea A, const LanePt
     bool inr = s < AB;
     if (OWN) inr = inr && (j > L.iloc);
     if (inr) {
-      const TabHit h = tab_lookup(tab32, lo, hi, sh, s);
+      const uint2 e = tb[max(__float_as_int(s) >> sh, lo)];
+      const bool ch = s >= __uint_as_float(e.y);
+      TabHit h;
+      h.unc = (s >= __uint_as_float(e.x)) && !ch;
+      h.slot = (int)(e.y & 63u) - 1 + (ch ? 1 : 0);
       if (!h.unc) atomicAdd(&A.hist[h.slot * 64 + lane], 1u);
       else {
         recheck_xi<SHIFT>(A, L, lane, U, j, sE, nb);
