@@ -1285,7 +1285,7 @@ void k_pairs(PairParams P) {
     for (int base = 0; base < total; base += 64) {
       const int t = base + lane;
       int keep = 0, pruned = 0, cell = 0, packed = 0, slots = 0, win = 0, wzlo = 0, wzhi = 0;
-      int mrg = 0;   // binary64 w_p: may join a run of z-cells (z-sorted, windows computable)
+      int mrg = 0;   // binary64: may join a run of z-cells (z-sorted, windows computable)
       if (t < total) {
         // column of the tile's list (order fixed by the host's split) and
         // z offset; an auto-count searches its own column forward in z only,
@@ -1378,14 +1378,14 @@ void k_pairs(PairParams P) {
                 hz = hz + 1e-9 * (fabs(blz) + fabs(bhz) + fabs(S2) + 1.0);
                 const double zl = blz - S2 - hz, zh = bhz - S2 + hz;
                 const bool cut = zl > B.lo[2] || zh < B.hi[2];
-                // (w_p: the window depends on the shift only, so the cells
-                // of a run share it; each keeps its bounds)
-                if (cut || (MODE == WP && PREC == F64)) {
+                // (a run of cells takes the union of their windows, so each
+                // keeps its bounds)
+                if (cut || PREC == F64) {
                   wzlo = __float_as_int(__double2float_rd(zl));
                   wzhi = __float_as_int(__double2float_ru(zh));
                 }
                 win = cut ? 1 : 0;
-                mrg = MODE == WP && PREC == F64 ? 1 : 0;
+                mrg = PREC == F64 && MODE != WPXI ? 1 : 0;
               }
             }
           }
@@ -1406,24 +1406,41 @@ void k_pairs(PairParams P) {
         const int pk = __builtin_amdgcn_readlane(packed, src);
         const int kc = __builtin_amdgcn_readlane(keep, src);
         const int sl = __builtin_amdgcn_readlane(slots, src);
-        // binary64 w_p: the following lanes' cells that continue this column
+        // binary64: the following lanes' cells that continue this column
         // upwards in z with the same shift and own flag join the unit (cells
         // are stored z-fastest, so the run's records are contiguous and,
         // z-sorted per cell, sorted as a whole; the binary64 loops read
         // absolute positions, while the binary32 records are in each cell's
-        // own frame, which a run would have to switch at every cell)
-        int nrun = 1, winr = kc & 128;
-        if (MODE == WP && PREC == F64 && (kc & 256)) {
+        // own frame, which a run would have to switch at every cell).  xi
+        // joins cells of the same slot range, or any cells the general loop
+        // takes (own, or more than three slots); the run's z-window is the
+        // union of its cells' windows.
+        int nrun = 1, winr = kc & 128, slr = sl;
+        float wl = 0.f, wh = 0.f;
+        if (PREC == F64 && MODE != WPXI && (kc & 256)) {
+          auto general = [&](int v, int p) {
+            return ((p >> 30) & 1) || ((v >> 8) & 255) - (v & 255) > 2;
+          };
+          const bool gen = MODE == XI && general(sl, pk);
           int last = src, pl = pk;
+          wl = __int_as_float(__builtin_amdgcn_readlane(wzlo, src));
+          wh = __int_as_float(__builtin_amdgcn_readlane(wzhi, src));
           while (last < 63 && ((mk >> (last + 1)) & 1ull)) {
             const int pk2 = __builtin_amdgcn_readlane(packed, last + 1);
             const int kc2 = __builtin_amdgcn_readlane(keep, last + 1);
             if (pk2 != pl + (1 << 20) || ((kc2 ^ kc) & 0x7E) || !(kc2 & 256)) break;
+            if (MODE == XI) {
+              const int sl2 = __builtin_amdgcn_readlane(slots, last + 1);
+              if (gen ? !general(sl2, pk2) : sl2 != sl) break;
+              slr = min(slr & 255, sl2 & 255) | (max((slr >> 8) & 255, (sl2 >> 8) & 255) << 8);
+            }
             last++;
             mk &= ~(1ull << last);
             nrun++;
             pl = pk2;
             winr |= kc2 & 128;
+            wl = fminf(wl, __int_as_float(__builtin_amdgcn_readlane(wzlo, last)));
+            wh = fmaxf(wh, __int_as_float(__builtin_amdgcn_readlane(wzhi, last)));
           }
         }
         const int X = pk & 1023, Y = (pk >> 10) & 1023, Z = (pk >> 20) & 1023;
@@ -1439,11 +1456,11 @@ void k_pairs(PairParams P) {
         U.pos = P.pos2 + pbase2;
         U.jb = CS[G2.sbase + c2];
         U.je = CS[G2.sbase + c2 + nrun];
-        U.slot_lo = sl & 255;
-        U.slot_hi = (sl >> 8) & 255;
+        U.slot_lo = slr & 255;
+        U.slot_hi = (slr >> 8) & 255;
         if (winr) {
-          const float zlo = __int_as_float(__builtin_amdgcn_readlane(wzlo, src));
-          const float zhi = __int_as_float(__builtin_amdgcn_readlane(wzhi, src));
+          const float zlo = nrun > 1 ? wl : __int_as_float(__builtin_amdgcn_readlane(wzlo, src));
+          const float zhi = nrun > 1 ? wh : __int_as_float(__builtin_amdgcn_readlane(wzhi, src));
           zwindow(U.pos, zlo, zhi, lane, U.jb, U.je);
           if (U.je <= U.jb) continue;
         }
