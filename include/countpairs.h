@@ -92,7 +92,7 @@ typedef struct {
                              library chooses the refine factors, the queue
                              items' work-chunk target and the waves per
                              workgroup by timing candidates on the call's own
-                             data (best of two whole calls each, coordinate
+                             data (best of three whole calls each, coordinate
                              descent), and caches the choice per workload
                              signature (statistic, precision, weights, periodic,
                              log2 of the point counts and of the expected

@@ -905,7 +905,7 @@ static int map_err_flags(int flags) {
 // refine = 0 on every axis leaves the launch settings to the library
 // (Section 3.1: the run time varies by up to 50 % with the refine factors,
 // whose automatic choice the paper names as future work).  Candidates are
-// timed on the call's own data -- device time of whole calls, best of two --
+// timed on the call's own data -- device time of whole calls, best of three --
 // by coordinate descent: the refine factors first, then the work-chunk
 // target of the queue items, then the waves per workgroup; the winner is
 // cached per workload signature (tune_cache.cpp).  CP_AUTOTUNE=0 switches
@@ -998,7 +998,7 @@ static int tune(const std::vector<Call> &calls, const std::string &key, TuneChoi
       w.assign(nout, 0.0);
       r.assign(nout, 0.0);
       double t = INFINITY;
-      for (int rep = 0; rep < 2; rep++) {
+      for (int rep = 0; rep < 3; rep++) {
         const int rc = run(c, n.data(), o.need_ravg ? w.data() : nullptr,
                            o.need_ravg ? r.data() : nullptr);
         if (rc) return rc;
