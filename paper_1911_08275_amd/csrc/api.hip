@@ -27,7 +27,8 @@ __global__ void k_colcount(const PointsDev *pts, const GridGeom *geom, int *mat,
 __global__ void k_colscatter(const PointsDev *pts, const GridGeom *geom, const int *off,
                              double4 *out);
 __global__ void k_colcells(const GridGeom *geom, const int *off, int stride, const double4 *colgrp,
-                           double4 *grp, int *cstart);
+                           double4 *grp, int *cstart, const int *maxspan,
+                           const int64_t *col_prefix, int *colcnt);
 __global__ void k_fill_u64(unsigned long long *p, int64_t n);
 __global__ void k_fill_f64(double *p, int64_t n);
 __global__ void k_scan_sums(const int *in, const ScanSeg *segs, int nseg, int *tsum);
@@ -577,10 +578,11 @@ static int launch_build(hipStream_t st, const PointsDev *d_pts, const GridGeom *
                         int64_t zero_words = 0) {
   (void)hipGetLastError();
   const char *ce = getenv("CP_BUILD_COLUMNS");
+  bool counted = false;   // the columns' tile counts are in colcnt already
   if (n > 0 && ncol <= kColLds && !(ce && ce[0] == '0')) {
     // grouping through LDS column histograms: the column x block counts in
     // colmat (scanned in place), column order in pos before the z pass
-    // overwrites it
+    // overwrites it; the per-column pass also counts the column's tiles
     if (zero_words)
       hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)std::min<int64_t>((zero_words + 255) / 256, 64)),
                          dim3(256), 0, st, zero, zero_words, 0);
@@ -593,7 +595,9 @@ static int launch_build(hipStream_t st, const PointsDev *d_pts, const GridGeom *
                        S.tsum);
     hipLaunchKernelGGL(k_colscatter, dim3(nb1), dim3(1024), 0, st, d_pts, d_geom, S.colmat, S.pos);
     hipLaunchKernelGGL(k_colcells, dim3((unsigned)std::min<int64_t>(ncol, 8192)), dim3(256), 0, st,
-                       d_geom, S.colmat, nb1, S.pos, S.grp, S.cstart);
+                       d_geom, S.colmat, nb1, S.pos, S.grp, S.cstart, d_maxspan, d_col_prefix,
+                       tiles ? S.colcnt : nullptr);
+    counted = tiles;
   } else {
     // the cell counters (and the caller's extra range) cleared by one launch
     const int64_t nfill = ncell * kCountStride;
@@ -620,8 +624,9 @@ static int launch_build(hipStream_t st, const PointsDev *d_pts, const GridGeom *
                        S.strm, S.cbox, d_win_prefix, mode);
   if (tiles) {
     const int tb = (int)std::min<int64_t>(std::max<int64_t>((ncol + 3) / 4, 1), 16384);
-    hipLaunchKernelGGL(k_tiles, dim3(tb), dim3(256), 0, st, d_geom, 1, S.cstart, d_maxspan,
-                       d_col_prefix, S.colcnt, S.coloff, S.tiles, 0);
+    if (!counted)
+      hipLaunchKernelGGL(k_tiles, dim3(tb), dim3(256), 0, st, d_geom, 1, S.cstart, d_maxspan,
+                         d_col_prefix, S.colcnt, S.coloff, S.tiles, 0);
     const unsigned tc = (unsigned)scan_tiles(ncol);
     if (tc > 1)
       hipLaunchKernelGGL(k_scan_sums, dim3(tc), dim3(256), 0, st, S.colcnt, d_seg_cols, 1, S.tsum);

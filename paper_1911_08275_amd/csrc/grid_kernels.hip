@@ -325,55 +325,6 @@ __global__ __launch_bounds__(1024) void k_colscatter(const PointsDev *pts, const
   }
 }
 
-// Pass 3: one workgroup per column (blockIdx.x, strided); column col spans
-// [off[col * stride], off[(col + 1) * stride]) of colgrp; grp in cell order,
-// cell starts into cstart.
-__global__ __launch_bounds__(256) void k_colcells(const GridGeom *geom, const int *off,
-                                                  int stride, const double4 *colgrp,
-                                                  double4 *grp, int *cstart) {
-  __shared__ int cnt[kMaxAxisCells + 1];
-  __shared__ int zs[kMaxAxisCells + 1];
-  const GridGeom &G = *geom;
-  const int ncol = G.n[0] * G.n[1], nz = G.n[2];
-  const int tid = threadIdx.x, lane = tid & 63;
-  for (int col = blockIdx.x; col < ncol; col += gridDim.x) {
-    const int c0 = off[(int64_t)col * stride], c1 = off[(int64_t)(col + 1) * stride];
-    for (int z = tid; z <= nz; z += blockDim.x) cnt[z] = 0;
-    __syncthreads();
-    for (int i = c0 + tid; i < c1; i += blockDim.x)
-      atomicAdd(&cnt[cell_coord(G, 2, colgrp[G.pbase + i].z)], 1);
-    __syncthreads();
-    // exclusive scan of the nz counts by wave 0, 64 at a time
-    if (tid < 64) {
-      int carry = 0;
-      for (int z0 = 0; z0 < nz; z0 += 64) {
-        const int v = z0 + lane < nz ? cnt[z0 + lane] : 0;
-        int x = v;
-#pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-          const int y = __shfl_up(x, d);
-          if (lane >= d) x += y;
-        }
-        if (z0 + lane < nz) zs[z0 + lane] = carry + x - v;
-        carry += __shfl(x, 63);
-      }
-    }
-    __syncthreads();
-    for (int z = tid; z < nz; z += blockDim.x) {
-      cstart[G.sbase + (int64_t)col * nz + z] = c0 + zs[z];
-      cnt[z] = 0;
-    }
-    if (col == ncol - 1 && tid == 0) cstart[G.sbase + (int64_t)ncol * nz] = c1;
-    __syncthreads();
-    for (int i = c0 + tid; i < c1; i += blockDim.x) {
-      const double4 v = colgrp[G.pbase + i];
-      const int z = cell_coord(G, 2, v.z);
-      grp[G.pbase + c0 + zs[z] + atomicAdd(&cnt[z], 1)] = v;
-    }
-    __syncthreads();
-  }
-}
-
 // Cell order, z ascending inside each cell (Section 2.1 contiguous per-cell
 // storage and z-sorted cells, used by the late entry / early exit of Section
 // 2.2).  k_group copies every point's (x, y, z, w) to its cell's range in the
@@ -758,6 +709,71 @@ __device__ inline void walk_column_lanes(const GridGeom &G, int csv, int lane, i
     }
     ntile++;
     p = q;
+  }
+}
+
+// Pass 3: one workgroup per column (blockIdx.x, strided); column col spans
+// [off[col * stride], off[(col + 1) * stride]) of colgrp; grp in cell order,
+// cell starts into cstart; with colcnt, the column's tile count too (the
+// walk of the tiles' counting pass, on the same cell starts).
+__global__ __launch_bounds__(256) void k_colcells(const GridGeom *geom, const int *off,
+                                                  int stride, const double4 *colgrp,
+                                                  double4 *grp, int *cstart, const int *maxspan,
+                                                  const int64_t *col_prefix, int *colcnt) {
+  __shared__ int cnt[kMaxAxisCells + 1];
+  __shared__ int zs[kMaxAxisCells + 1];
+  const GridGeom &G = *geom;
+  const int ncol = G.n[0] * G.n[1], nz = G.n[2];
+  const int tid = threadIdx.x, lane = tid & 63;
+  for (int col = blockIdx.x; col < ncol; col += gridDim.x) {
+    const int c0 = off[(int64_t)col * stride], c1 = off[(int64_t)(col + 1) * stride];
+    for (int z = tid; z <= nz; z += blockDim.x) cnt[z] = 0;
+    __syncthreads();
+    for (int i = c0 + tid; i < c1; i += blockDim.x)
+      atomicAdd(&cnt[cell_coord(G, 2, colgrp[G.pbase + i].z)], 1);
+    __syncthreads();
+    // exclusive scan of the nz counts by wave 0, 64 at a time
+    if (tid < 64) {
+      int carry = 0;
+      for (int z0 = 0; z0 < nz; z0 += 64) {
+        const int v = z0 + lane < nz ? cnt[z0 + lane] : 0;
+        int x = v;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+          const int y = __shfl_up(x, d);
+          if (lane >= d) x += y;
+        }
+        if (z0 + lane < nz) zs[z0 + lane] = carry + x - v;
+        carry += __shfl(x, 63);
+      }
+    }
+    __syncthreads();
+    for (int z = tid; z < nz; z += blockDim.x) {
+      cstart[G.sbase + (int64_t)col * nz + z] = c0 + zs[z];
+      cnt[z] = 0;
+    }
+    if (col == ncol - 1 && tid == 0) cstart[G.sbase + (int64_t)ncol * nz] = c1;
+    __syncthreads();
+    for (int i = c0 + tid; i < c1; i += blockDim.x) {
+      const double4 v = colgrp[G.pbase + i];
+      const int z = cell_coord(G, 2, v.z);
+      grp[G.pbase + c0 + zs[z] + atomicAdd(&cnt[z], 1)] = v;
+    }
+    __syncthreads();
+    if (colcnt) {
+      for (int z = tid; z <= nz; z += blockDim.x) zs[z] = z < nz ? c0 + zs[z] : c1;
+      __syncthreads();
+      if (tid < 64) {
+        int64_t n = 0;
+        if (nz < 64) {
+          walk_column_lanes(G, zs[min(lane, nz)], lane, col, *maxspan, 0, 0, nullptr, n);
+        } else if (lane == 0) {
+          walk_column(G, zs, col, *maxspan, 0, 0, nullptr, n);
+        }
+        if (lane == 0) colcnt[col_prefix[0] + column_rank(col, G.n[0], G.n[1])] = (int)n;
+      }
+      __syncthreads();
+    }
   }
 }
 
