@@ -230,11 +230,14 @@ int countpairs_last_stats(cp_stats *out);
 /*
  * Batched plan: many catalogues of uneven size counted together (Section 1.1
  * motivates many correlation-function evaluations, e.g. inside MCMC).  All
- * catalogues share the periodic box, the bins and the precision.  One
- * execute enqueues, on one stream, the cell build of every catalogue and one
- * persistent pair launch for xi and one for wp that drain a shared queue of
- * tiles ordered by decreasing cost.  Execute allocates nothing and is safe
- * to capture in a hipGraph; the plan owns all scratch memory.
+ * catalogues share the periodic box, the bins and the precision; plans
+ * count pairs only (the catalogues' weights are not read).  One execute
+ * enqueues, on one stream, the cell build of every catalogue and persistent
+ * pair launches that drain a shared queue of tiles ordered by decreasing
+ * cost: one for xi and one for wp, or, in binary32 when every xi pair lies
+ * inside the wp search (xi R_max at most r_p,max and pi_max), one launch that
+ * counts both.  Execute allocates nothing and is safe to capture in a
+ * hipGraph; the plan owns all scratch memory.
  *
  *   cp_plan_create   mocks: nmocks point sets (device pointers read at every
  *                    execute, so the caller may refill them in place);
@@ -242,7 +245,9 @@ int countpairs_last_stats(cp_stats *out);
  *                    o: precision, refine, periodic (must be 1) and boxsize.
  *                    refine 0: the settings are tuned (and cached) by timing
  *                    single calls of the requested statistics on the median
- *                    catalogue.
+ *                    catalogue, or, for the single binary32 launch, trial
+ *                    plans of up to four catalogues picked at even quantiles
+ *                    of the pair work (n^2).
  *   cp_plan_execute  enqueue one evaluation on stream (asynchronous).
  *   cp_plan_results  synchronise the stream of the last execute and copy counts:
  *                    xi_npairs nmocks*(xi_nedges-1), wp_npairs
