@@ -26,7 +26,7 @@ __global__ void k_fill2_i32(int *a, int64_t na, int *b, int64_t nb);
 __global__ void k_colcount(const PointsDev *pts, const GridGeom *geom, int *mat, int *err);
 __global__ void k_colscatter(const PointsDev *pts, const GridGeom *geom, const int *off,
                              double4 *out);
-__global__ void k_colcells(const GridGeom *geom, const int *off, int stride, const double4 *colgrp,
+__global__ void k_colcells(const GridGeom *geom, const int *off, const double4 *colgrp,
                            double4 *grp, int *cstart, const int *maxspan,
                            const int64_t *col_prefix, int *colcnt);
 __global__ void k_fill_u64(unsigned long long *p, int64_t n);
@@ -377,6 +377,8 @@ static GridGeom to_dev_geom(const Geometry &g, bool periodic, double box, int64_
   G.ncell = g.n[0] * g.n[1] * g.n[2];
   G.ncol = g.n[0] * g.n[1];
   G.colbase = colbase;
+  G.mbase = 0;
+  G.nblk = col_blocks(npts);
   return G;
 }
 
@@ -595,7 +597,7 @@ static int launch_build(hipStream_t st, const PointsDev *d_pts, const GridGeom *
                        S.tsum);
     hipLaunchKernelGGL(k_colscatter, dim3(nb1), dim3(1024), 0, st, d_pts, d_geom, S.colmat, S.pos);
     hipLaunchKernelGGL(k_colcells, dim3((unsigned)std::min<int64_t>(ncol, 8192)), dim3(256), 0, st,
-                       d_geom, S.colmat, nb1, S.pos, S.grp, S.cstart, d_maxspan, d_col_prefix,
+                       d_geom, S.colmat, S.pos, S.grp, S.cstart, d_maxspan, d_col_prefix,
                        tiles ? S.colcnt : nullptr);
     counted = tiles;
   } else {
@@ -1632,10 +1634,16 @@ struct Batch {
   std::vector<ScanSeg> segs;      // nmock cell segments, then 1 column segment
   std::vector<int64_t> win_prefix, col_prefix;
   std::vector<int> maxspan;
+  // column build (grids of up to kColLds columns): one column x block matrix
+  // per catalogue, nmock scan segments over them
+  bool colpath = false;
+  std::vector<ScanSeg> msegs;
+  int64_t nmat_tot = 0, mtiles = 0;
+  int maxnb = 1;
   // device
   GridGeom *d_geom = nullptr;
   PointsDev *d_pts = nullptr;
-  ScanSeg *d_segs = nullptr;
+  ScanSeg *d_segs = nullptr, *d_msegs = nullptr;
   int64_t *d_win_prefix = nullptr, *d_col_prefix = nullptr;
   int *d_maxspan = nullptr;
   SetBufs S{};
@@ -1718,6 +1726,24 @@ static int batch_prepare(cp_plan &pl, Batch &b, int mode, int prec, const double
   b.ncell_tot = b.ncell * pl.nmock;
   b.ncol_tot = b.ncol * pl.nmock;
   b.segs.push_back({0, 0, b.ncol_tot, 0, 1});
+  // the column build, as for single calls: each catalogue's matrix holds
+  // ncol * nblk counts and, after its scan, the total (one more word)
+  const char *ce = getenv("CP_BUILD_COLUMNS");
+  b.colpath = b.ncol <= kColLds && !(ce && ce[0] == '0');
+  b.msegs.clear();
+  b.nmat_tot = 0;
+  b.mtiles = 0;
+  b.maxnb = 1;
+  if (b.colpath) {
+    for (GridGeom &G : b.geoms) {
+      G.mbase = b.nmat_tot;
+      const int64_t len = b.ncol * G.nblk;
+      b.msegs.push_back({G.mbase, G.mbase, len, b.mtiles, 1});
+      b.mtiles += scan_tiles(len);
+      b.nmat_tot += len + 1;
+      b.maxnb = std::max(b.maxnb, G.nblk);
+    }
+  }
   b.maxtiles = max_tiles_bound(b.npts_tot, b.ncell_tot, b.ncol_tot);
   b.wpc = wp_copies(mode, b.prec, 0, (int)b.B.t32.e.size(), (int)b.B.t64.e.size(), b.nb, b.npi);
   const LdsLayout LY = lds_layout(mode, b.prec, 0, (int)b.B.t32.e.size(),
@@ -1733,12 +1759,15 @@ static void batch_carve(Carver &cv, cp_plan &pl, Batch &b) {
   b.d_geom = cv.take<GridGeom>(nm);
   b.d_pts = cv.take<PointsDev>(nm);
   b.d_segs = cv.take<ScanSeg>(nm + 1);
+  b.d_msegs = cv.take<ScanSeg>(b.colpath ? nm : 1);
   b.d_win_prefix = cv.take<int64_t>(nm + 1);
   b.d_col_prefix = cv.take<int64_t>(nm + 1);
   b.d_maxspan = cv.take<int>(nm);
   // cell_start needs ncell + 1 per catalogue
   b.S.ccount = cv.take<int>(b.ncell_tot * kCountStride);
-  b.S.tsum = cv.take<int>(std::max(scan_tiles(b.ncell) * nm, scan_tiles(b.ncol_tot)));
+  b.S.tsum = cv.take<int>(
+      std::max({scan_tiles(b.ncell) * nm, scan_tiles(b.ncol_tot), b.colpath ? b.mtiles : 1}));
+  b.S.colmat = cv.take<int>(b.colpath ? b.nmat_tot : 1);
   b.S.cstart = cv.take<int>(b.ncell_tot + nm);
   b.S.cid = cv.take<int>(std::max<int64_t>(b.npts_tot, 1));
   b.S.rank = cv.take<int>(std::max<int64_t>(b.npts_tot, 1));
@@ -1767,6 +1796,8 @@ static int batch_upload(cp_plan &pl, Batch &b) {
   HIPCHK(hipMemcpy(b.d_geom, b.geoms.data(), sizeof(GridGeom) * nm, hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(b.d_pts, pl.pts.data(), sizeof(PointsDev) * nm, hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(b.d_segs, b.segs.data(), sizeof(ScanSeg) * (nm + 1), hipMemcpyHostToDevice));
+  if (b.colpath)
+    HIPCHK(hipMemcpy(b.d_msegs, b.msegs.data(), sizeof(ScanSeg) * nm, hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(b.d_win_prefix, b.win_prefix.data(), 8 * (nm + 1), hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(b.d_col_prefix, b.col_prefix.data(), 8 * (nm + 1), hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(b.d_maxspan, b.maxspan.data(), 4 * nm, hipMemcpyHostToDevice));
@@ -1838,26 +1869,46 @@ static int batch_enqueue(cp_plan &pl, Batch &b, hipStream_t st) {
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, b.d_err, (int64_t)1, 0);
     return hipGetLastError() == hipSuccess ? CP_OK : fail(CP_ERR_DEVICE, "launch failed");
   }
-  hipLaunchKernelGGL(k_fill_i32, dim3(blocks(b.ncell_tot * kCountStride, 256, 8192)), dim3(256), 0,
-                     st, b.S.ccount, b.ncell_tot * kCountStride, 0);
+  if (!b.colpath)
+    hipLaunchKernelGGL(k_fill_i32, dim3(blocks(b.ncell_tot * kCountStride, 256, 8192)), dim3(256),
+                       0, st, b.S.ccount, b.ncell_tot * kCountStride, 0);
   hipLaunchKernelGGL(k_fill_u64, dim3(blocks((int64_t)b.nout * nm, 256, 1024)), dim3(256), 0, st,
                      b.d_hist, (int64_t)b.nout * nm);
   hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, b.d_stats, (int64_t)kStatWords);
   hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, b.d_err, (int64_t)1, 0);
-  hipLaunchKernelGGL(k_assign, dim3(blocks(pl.maxn, 256, 4096), nm), dim3(256), 0, st, b.d_pts,
-                     b.d_geom, b.S.ccount, b.S.cid, b.S.rank, b.d_err);
-  const unsigned sc = (unsigned)(scan_tiles(b.ncell) * nm);
-  hipLaunchKernelGGL(k_scan_sums, dim3(sc), dim3(256), 0, st, b.S.ccount, b.d_segs, nm, b.S.tsum);
-  hipLaunchKernelGGL(k_scan_apply, dim3(sc), dim3(256), 0, st, b.S.ccount, b.S.cstart, b.d_segs,
-                     nm, b.S.tsum);
-  hipLaunchKernelGGL(k_group, dim3(blocks(pl.maxn, 256, 4096), nm), dim3(256), 0, st, b.d_pts,
-                     b.d_geom, b.S.cstart, b.S.cid, b.S.rank, b.S.grp);
+  if (b.colpath) {
+    // every catalogue's column build at once (blockIdx.y = catalogue); the
+    // per-column pass also counts the columns' tiles
+    hipLaunchKernelGGL(k_colcount, dim3(b.maxnb, nm), dim3(1024), 0, st, b.d_pts, b.d_geom,
+                       b.S.colmat, b.d_err);
+    const unsigned tm = (unsigned)b.mtiles;
+    hipLaunchKernelGGL(k_scan_sums, dim3(tm), dim3(256), 0, st, b.S.colmat, b.d_msegs, nm,
+                       b.S.tsum);
+    hipLaunchKernelGGL(k_scan_apply, dim3(tm), dim3(256), 0, st, b.S.colmat, b.S.colmat,
+                       b.d_msegs, nm, b.S.tsum);
+    hipLaunchKernelGGL(k_colscatter, dim3(b.maxnb, nm), dim3(1024), 0, st, b.d_pts, b.d_geom,
+                       b.S.colmat, b.S.pos);
+    hipLaunchKernelGGL(k_colcells, dim3((unsigned)std::min<int64_t>(b.ncol, 8192), nm), dim3(256),
+                       0, st, b.d_geom, b.S.colmat, b.S.pos, b.S.grp, b.S.cstart, b.d_maxspan,
+                       b.d_col_prefix, b.S.colcnt);
+  } else {
+    hipLaunchKernelGGL(k_assign, dim3(blocks(pl.maxn, 256, 4096), nm), dim3(256), 0, st, b.d_pts,
+                       b.d_geom, b.S.ccount, b.S.cid, b.S.rank, b.d_err);
+    const unsigned sc = (unsigned)(scan_tiles(b.ncell) * nm);
+    hipLaunchKernelGGL(k_scan_sums, dim3(sc), dim3(256), 0, st, b.S.ccount, b.d_segs, nm,
+                       b.S.tsum);
+    hipLaunchKernelGGL(k_scan_apply, dim3(sc), dim3(256), 0, st, b.S.ccount, b.S.cstart,
+                       b.d_segs, nm, b.S.tsum);
+    hipLaunchKernelGGL(k_group, dim3(blocks(pl.maxn, 256, 4096), nm), dim3(256), 0, st, b.d_pts,
+                       b.d_geom, b.S.cstart, b.S.cid, b.S.rank, b.S.grp);
+  }
   hipLaunchKernelGGL(k_cellsort, dim3(blocks(b.win_prefix[nm], 4, 65536)), dim3(256), 0, st,
                      b.d_geom, nm, b.S.cstart, b.S.grp, b.S.pos, b.S.strm, b.S.cbox, b.d_win_prefix,
                      b.mode);
   const int tb = blocks(b.ncol_tot, 4, 65536);
-  hipLaunchKernelGGL(k_tiles, dim3(tb), dim3(256), 0, st, b.d_geom, nm, b.S.cstart, b.d_maxspan,
-                     b.d_col_prefix, b.S.colcnt, b.S.coloff, b.S.tiles, 0);
+  if (!b.colpath)
+    hipLaunchKernelGGL(k_tiles, dim3(tb), dim3(256), 0, st, b.d_geom, nm, b.S.cstart, b.d_maxspan,
+                       b.d_col_prefix, b.S.colcnt, b.S.coloff, b.S.tiles, 0);
   const unsigned tcol = (unsigned)scan_tiles(b.ncol_tot);
   hipLaunchKernelGGL(k_scan_sums, dim3(tcol), dim3(256), 0, st, b.S.colcnt, b.d_segs + nm, 1,
                      b.S.tsum);

@@ -102,6 +102,8 @@ struct GridGeom {
   int ncell;
   int ncol;
   int64_t colbase; // first entry of this catalogue in per-column arrays
+  int64_t mbase;   // first entry of this catalogue's column x block matrix (column build)
+  int nblk;        // blocks of the column build for this catalogue
 };
 
 // Input point set on the device (one catalogue).

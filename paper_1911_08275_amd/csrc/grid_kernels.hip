@@ -280,13 +280,17 @@ __device__ inline void block_chunk(int64_t n, int b, int nb, int64_t &i0, int64_
   i1 = min(n, i0 + per);
 }
 
-// Pass 1 (validates the points as k_assign does); one catalogue.
+// One catalogue per blockIdx.y, its G.nblk blocks along x (blocks beyond
+// them return), its matrix at mat + G.mbase.
+// Pass 1 (validates the points as k_assign does).
 __global__ __launch_bounds__(1024) void k_colcount(const PointsDev *pts, const GridGeom *geom,
                                                    int *mat, int *err) {
   __shared__ int h[kColLds];
-  const PointsDev P = *pts;
-  const GridGeom &G = *geom;
-  const int ncol = G.n[0] * G.n[1], nb = gridDim.x;
+  const PointsDev P = pts[blockIdx.y];
+  const GridGeom &G = geom[blockIdx.y];
+  const int ncol = G.n[0] * G.n[1], nb = G.nblk;
+  if ((int)blockIdx.x >= nb) return;   // uniform over the block
+  mat += G.mbase;
   for (int c = threadIdx.x; c < ncol; c += blockDim.x) h[c] = 0;
   __syncthreads();
   int64_t i0, i1;
@@ -311,9 +315,11 @@ __global__ __launch_bounds__(1024) void k_colcount(const PointsDev *pts, const G
 __global__ __launch_bounds__(1024) void k_colscatter(const PointsDev *pts, const GridGeom *geom,
                                                      const int *off, double4 *out) {
   __shared__ int base[kColLds];
-  const PointsDev P = *pts;
-  const GridGeom &G = *geom;
-  const int ncol = G.n[0] * G.n[1], nb = gridDim.x;
+  const PointsDev P = pts[blockIdx.y];
+  const GridGeom &G = geom[blockIdx.y];
+  const int ncol = G.n[0] * G.n[1], nb = G.nblk;
+  if ((int)blockIdx.x >= nb) return;   // uniform over the block
+  off += G.mbase;
   for (int c = threadIdx.x; c < ncol; c += blockDim.x) base[c] = off[(int64_t)c * nb + blockIdx.x];
   __syncthreads();
   int64_t i0, i1;
@@ -712,17 +718,21 @@ __device__ inline void walk_column_lanes(const GridGeom &G, int csv, int lane, i
   }
 }
 
-// Pass 3: one workgroup per column (blockIdx.x, strided); column col spans
-// [off[col * stride], off[(col + 1) * stride]) of colgrp; grp in cell order,
-// cell starts into cstart; with colcnt, the column's tile count too (the
-// walk of the tiles' counting pass, on the same cell starts).
+// Pass 3: one workgroup per column (blockIdx.x, strided; catalogue
+// blockIdx.y); column col spans [off[col * nblk], off[(col + 1) * nblk]) of
+// colgrp (off = the catalogue's scanned matrix); grp in cell order, cell
+// starts into cstart; with colcnt, the column's tile count too (the walk of
+// the tiles' counting pass, on the same cell starts).
 __global__ __launch_bounds__(256) void k_colcells(const GridGeom *geom, const int *off,
-                                                  int stride, const double4 *colgrp,
-                                                  double4 *grp, int *cstart, const int *maxspan,
+                                                  const double4 *colgrp, double4 *grp,
+                                                  int *cstart, const int *maxspan,
                                                   const int64_t *col_prefix, int *colcnt) {
   __shared__ int cnt[kMaxAxisCells + 1];
   __shared__ int zs[kMaxAxisCells + 1];
-  const GridGeom &G = *geom;
+  const int mock = blockIdx.y;
+  const GridGeom &G = geom[mock];
+  const int stride = G.nblk;
+  off += G.mbase;
   const int ncol = G.n[0] * G.n[1], nz = G.n[2];
   const int tid = threadIdx.x, lane = tid & 63;
   for (int col = blockIdx.x; col < ncol; col += gridDim.x) {
@@ -766,11 +776,11 @@ __global__ __launch_bounds__(256) void k_colcells(const GridGeom *geom, const in
       if (tid < 64) {
         int64_t n = 0;
         if (nz < 64) {
-          walk_column_lanes(G, zs[min(lane, nz)], lane, col, *maxspan, 0, 0, nullptr, n);
+          walk_column_lanes(G, zs[min(lane, nz)], lane, col, maxspan[mock], mock, 0, nullptr, n);
         } else if (lane == 0) {
-          walk_column(G, zs, col, *maxspan, 0, 0, nullptr, n);
+          walk_column(G, zs, col, maxspan[mock], mock, 0, nullptr, n);
         }
-        if (lane == 0) colcnt[col_prefix[0] + column_rank(col, G.n[0], G.n[1])] = (int)n;
+        if (lane == 0) colcnt[col_prefix[mock] + column_rank(col, G.n[0], G.n[1])] = (int)n;
       }
       __syncthreads();
     }
