@@ -443,6 +443,38 @@ def test_build_paths_agree(native, monkeypatch):
     _check(out["1"][3], ref, weighted=True, prec="fp32", periodic=False)
 
 
+def test_plan_build_paths_agree(native, monkeypatch):
+    """Plans build all catalogues' cells with the column kernels at once
+    (catalogue = blockIdx.y, a matrix and scan segment each, an empty
+    catalogue among them); the atomic grouping (CP_BUILD_COLUMNS=0) gives the
+    same counts, and both equal single calls."""
+    cats = _mock_set()
+    cats.append(synth.Catalog(np.zeros(0), np.zeros(0), np.zeros(0), None))
+    xe = synth.log_edges(0.1, 25.0, 14)
+    devs = [native.to_device(c) for c in cats]
+    out = {}
+    for path in ("1", "0"):
+        monkeypatch.setenv("CP_BUILD_COLUMNS", path)
+        _say("plan build path", path)
+        for prec in ("fp32", "fp64"):
+            plan = native.Plan(devs, xi_edges=xe, wp_edges=xe, pimax=40.0, npibins=40,
+                               precision=prec, periodic=True, boxsize=420.0, refine=(2, 2, 2))
+            plan.execute()
+            out[path, prec] = plan.results()
+            plan.close()
+    for prec in ("fp32", "fp64"):
+        for a, b in zip(out["1", prec], out["0", prec]):
+            assert (a == b).all()
+    xi, wp = out["1", "fp32"]
+    assert xi[-1].sum() == 0 and wp[-1].sum() == 0
+    for m in range(len(cats) - 1):
+        s = native.countpairs_xi(devs[m], xe, precision="fp64", periodic=True, boxsize=420.0)
+        assert (s.npairs == xi[m]).all()
+        s = native.countpairs_wp(devs[m], xe, 40.0, 40, precision="fp64", periodic=True,
+                                 boxsize=420.0)
+        assert (s.npairs == wp[m]).all()
+
+
 def test_unique_mode_and_pruning_stats(native):
     cat = synth.clustered(30_000, 600, 1.5, 420.0, seed=6)
     edges = synth.log_edges(0.1, 25.0, 14)
