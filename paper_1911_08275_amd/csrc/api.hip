@@ -749,7 +749,7 @@ struct Binning {
   float AB32;
   float eps32, eps32_3;
   Bounds bnd;
-  float inv_dpi32, pi_delta, pi_hi32;
+  float inv_dpi32, pi_delta, pi_hi32, pi_delta64;
   double dpi;
 };
 
@@ -801,10 +801,13 @@ static int make_binning(int mode, int prec, const double *edges, int nedges, dou
     // edges; it also covers pi_max itself, whose edge is the integer npi, so
     // a pair away from every integer is surely below pi_max
     B.pi_delta = (float)(B.bnd.eta_pi / B.dpi + 8 * u * npi + 1e-12 * npi);
+    // the binary64 loops bin fl32(|dz|) of the binary64 |dz| < pi_max the
+    // same way: its error is at most u |dz| < u pi_max (1.01 for margin)
+    B.pi_delta64 = (float)(1.01 * u * pimax / B.dpi + 8 * u * npi + 1e-12 * npi);
     B.pi_hi32 = f32_up(pimax + B.bnd.eta_pi);
   } else {
     B.inv_dpi32 = 1.0f;
-    B.pi_delta = 0.f;
+    B.pi_delta = B.pi_delta64 = 0.f;
     B.pi_hi32 = 0.f;
   }
   return CP_OK;
@@ -1342,6 +1345,7 @@ static int run(const Call &c, uint64_t *npairs, double *wsum, double *ravg) {
   P.npi = npi;
   P.inv_dpi32 = B.inv_dpi32;
   P.pi_delta = B.pi_delta;
+  P.pi_delta64 = B.pi_delta64;
   P.pi_hi32 = B.pi_hi32;
   P.autocorr = autoc ? 1 : 0;
   P.weighted = weighted ? 1 : 0;
@@ -1844,6 +1848,7 @@ static int batch_upload(cp_plan &pl, Batch &b) {
   P.wpc = b.wpc;
   P.inv_dpi32 = b.B.inv_dpi32;
   P.pi_delta = b.B.pi_delta;
+  P.pi_delta64 = b.B.pi_delta64;
   P.pi_hi32 = b.B.pi_hi32;
   P.autocorr = 1;
   P.weighted = 0;

@@ -166,6 +166,7 @@ struct PairParams {
   int npi;
   int wpc;                   // copies of the wave's histogram (power of two)
   float inv_dpi32, pi_delta, pi_hi32;
+  float pi_delta64;          // pi band of the binary64 loops' binary32 pi bin
   // flags
   int autocorr;
   int weighted;

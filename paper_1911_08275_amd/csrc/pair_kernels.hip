@@ -103,6 +103,18 @@ __device__ inline int exact_pibin(double pz, double dpi, double inv_dpi, int npi
   return l;
 }
 
+// Pi bin of a binary64 |dz| < pi_max through binary32: f = fl32(fl32(|dz|) *
+// fl32(1 / dpi)) and bin floor(f), unless the fraction of f lies within pd of
+// an integer (the band of the binary32 loops with the estimate's error
+// u |dz| < u pi_max), where exact_pibin decides.
+__device__ inline int pibin_fast(double pz, float inv32, float pd, float pd1, double dpi,
+                                 double inv_dpi, int npi) {
+  const float f = (float)pz * inv32;
+  const float fr = __builtin_amdgcn_fractf(f);   // f - floor(f), exact for f >= 0
+  if (fr < pd || fr > pd1) return exact_pibin(pz, dpi, inv_dpi, npi);
+  return (int)f;
+}
+
 // Table lookup: slot for v (binary32 estimate), or uncertain.
 struct TabHit {
   int slot;
@@ -1110,6 +1122,7 @@ __device__ inline void loop_f64(const PairParams &P, WaveArea A, const LanePt &L
   const int lo = P.tab64_lo, sh = P.tab_shift;
   const uint2 *tb = tab64 - lo;
   const int nb = P.nb, npi = P.npi;
+  const float inv32 = P.inv_dpi32, pd = P.pi_delta64, pd1 = 1.0f - P.pi_delta64;
   stream_f64(U.pos, U.jb, U.je, [&](int j, double ux, double uy, double uz, double uw) {
     double dx, dy, dz;
     ref_sep<SHIFT, WRAP>(L.x, L.y, L.z, ux, uy, uz, U.S, wrapax, box, half, dx, dy, dz);
@@ -1132,7 +1145,7 @@ __device__ inline void loop_f64(const PairParams &P, WaveArea A, const LanePt &L
       if (OWN) inr = inr && (j > L.iloc);
       if (inr) {
         const int slot = slot64_below(tb, lo, sh, sE, nb, rp2);
-        const int l = exact_pibin(pz64, P.dpi, P.inv_dpi, npi);
+        const int l = pibin_fast(pz64, inv32, pd, pd1, P.dpi, P.inv_dpi, npi);
         const int c = (slot * npi + l) * P.wpc + (lane & (P.wpc - 1));
         atomicAdd(&A.hist[c], 1u);
         if (W) {

@@ -252,3 +252,35 @@ def test_pi_binary32_decision(seed):
             assert np.all(dz[certain] < pimax)
             assert np.array_equal(np.floor(f[certain]).astype(np.int64), truebin[certain])
     assert counted > 10000
+
+
+@pytest.mark.parametrize("seed", [43, 44])
+def test_pi_bin_binary64_through_binary32(seed):
+    """The binary64 w_p loops bin a binary64 |dz| < pi_max through binary32:
+    f = fl32(fl32(|dz|) * fl32(1 / dpi)), bin floor(f) unless the fraction of
+    f lies within pi_delta64 = 1.01 u pi_max / dpi + 8 u npi (+1e-12 npi) of
+    an integer.  Every bin so taken must be the bin of |dz| under the binary64
+    edges, on |dz| at and around every edge and just below pi_max."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    counted = 0
+    for _ in range(150):
+        pimax = float(rng.uniform(0.5, 300.0))
+        npi = int(rng.integers(1, 257))
+        dpi = pimax / npi
+        inv = np.float32(1.0 / dpi)
+        pd = np.float32(1.01 * U * pimax / dpi + 8 * U * npi + 1e-12 * npi)
+        pd1 = np.float32(np.float32(1.0) - pd)
+        q = np.array([l * dpi for l in range(1, npi)] + [pimax])
+        base = np.concatenate([q, np.nextafter(q, 0.0), np.nextafter(q, np.inf),
+                               rng.uniform(0.0, pimax, 300)])
+        step = dpi * np.array([-1e-4, -1e-5, -1e-6, -1e-7, 0.0, 1e-7, 1e-6, 1e-5, 1e-4])
+        dz = (base[:, None] + step[None, :]).ravel()
+        dz = dz[(dz >= 0.0) & (dz < pimax)]
+        truebin = np.searchsorted(q[:-1], dz, side="right")
+        f = dz.astype(np.float32) * inv
+        fr = f - np.floor(f)
+        certain = (fr >= pd) & (fr <= pd1)
+        counted += int(certain.sum())
+        assert np.array_equal(np.floor(f[certain]).astype(np.int64), truebin[certain])
+        assert np.all(np.floor(f[certain]) <= npi - 1)
+    assert counted > 10000
