@@ -11,8 +11,9 @@
 // pairs of points by sorted index), skips cells whose bounding box is too
 // far from the tile's (Section 2.2, minimum possible separation), cuts each
 // remaining (tile, cell) unit to a z-window on the z-sorted cell (Section
-// 2.2, late entry and early exit), and streams the unit's points through the
-// scalar cache, so every VALU instruction of the inner loop takes one
+// 2.2, late entry and early exit; the binary64 loops join consecutive
+// z-cells of a column into one unit), and streams the unit's points through
+// the scalar cache, so every VALU instruction of the inner loop takes one
 // wave-uniform operand from SGPRs and one per-lane operand from VGPRs.
 //
 // Inner loop, binary32 mode.  Coordinates are held relative to the streamed
